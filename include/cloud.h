@@ -1,0 +1,193 @@
+/*
+ * cloud.h -- C ABI of the MI355X (gfx950) cloud raymarch library.
+ *
+ * The library renders the volumetric-cloud method of Toft, Bowles and
+ * Zimmermann, "Optimisations for Real-Time Volumetric Cloudscapes"
+ * (arXiv 1609.05344): a per-pixel primary raymarch through a 3-D density
+ * field (Section 1) with a per-pixel jittered start (Section 3.2), a
+ * Beer-Lambert light march towards the sun at each sample, Henyey-Greenstein
+ * phase plus an ambient term (Section 1), the analytic integration of
+ * scattering over each step (Section 3.1), and a temporal resolve that
+ * accumulates the jittered frames (Section 3.2).
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: CLOUD_OK (0) or a negative CLOUD_E_* code. No C++
+ *    exception crosses this boundary. cloud_last_error() returns a
+ *    thread-local message describing the last non-OK result on the calling
+ *    thread.
+ *  - Pointers marked "device" are HIP device memory owned by the caller; the
+ *    library never frees them and never keeps them beyond the call, except a
+ *    server's shared volume (see cloud_serve_create). Struct arguments are
+ *    host memory, read during the call only.
+ *  - Every argument is checked on the host before anything is launched; an
+ *    invalid call returns CLOUD_E_INVALID and launches nothing.
+ *  - Render and resolve calls are asynchronous: work is enqueued on the given
+ *    HIP stream (a hipStream_t passed as void*, NULL for the default stream)
+ *    and the call returns. A launch failure is CLOUD_E_HIP; a fault during
+ *    execution surfaces at the caller's next synchronisation.
+ *  - Identical inputs give bitwise-identical outputs (no floating-point
+ *    atomics; every output element is written by exactly one thread).
+ *  - Images are [height][width][4] float32 RGBA, row 0 at the top, 16-byte
+ *    aligned. Colour is premultiplied by opacity; alpha = 1 - T, where T is
+ *    the transmittance along the view ray. No background is composited.
+ */
+#ifndef CLOUD_H
+#define CLOUD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CLOUD_ABI_VERSION 1
+
+enum {
+  CLOUD_OK = 0,
+  CLOUD_E_INVALID = -1,   /* bad argument; nothing launched */
+  CLOUD_E_NOMEM = -2,     /* allocation failed, or request can never fit a budget */
+  CLOUD_E_HIP = -3,       /* HIP runtime error (launch, copy, event) */
+  CLOUD_E_BUSY = -4,      /* server queue full; retry later */
+  CLOUD_E_NOTFOUND = -5,  /* unknown stream or request id */
+  CLOUD_E_CANCELLED = -6  /* request dropped by cloud_serve_destroy */
+};
+
+/* Storage type of a density volume. Every type is decoded exactly to
+ * float32; all optical depth, transmittance, exponentials and colour are
+ * accumulated in float32. */
+enum { CLOUD_F32 = 0, CLOUD_F16 = 1, CLOUD_BF16 = 2 };
+
+/* Density field (Section 1: "the density is sampled" at each step).
+ *  base    device, [nz][ny][nx] values of type dtype, x fastest, y up. Texel
+ *          (i,j,k) is centred at box_min + (i+0.5, j+0.5, k+0.5) * extent/n.
+ *          Lookups are trilinear (x, then y, then z) with clamp-to-edge.
+ *  detail  device, optional (NULL = none), [dnz][dny][dnx] of type ddtype,
+ *          tiled detail_tiling times across the box with repeat addressing.
+ *          With detail the density is
+ *          clamp((b - detail_weight*d) / (1 - detail_weight*d), 0, 1).
+ *  Requirements: n* >= 2, dn* >= 2 when detail is set, box_max > box_min on
+ *  every axis, 0 <= detail_weight < 1, detail_tiling > 0, values in [0, 1]
+ *  for detail. The volume must stay valid until the call's work has run.
+ *  layout must be 0 (dense [nz][ny][nx]). */
+typedef struct {
+  const void* base;
+  int32_t nx, ny, nz;
+  int32_t dtype;
+  const void* detail;
+  int32_t dnx, dny, dnz;
+  int32_t ddtype;
+  float detail_weight;
+  float detail_tiling;
+  float box_min[3];
+  float box_max[3];
+  int32_t layout;
+} cloud_volume;
+
+/* Pinhole camera: rays leave pos through pixel centres; vfov_deg is the
+ * vertical field of view; up fixes the roll (it must not be parallel to
+ * target - pos). */
+typedef struct {
+  float pos[3];
+  float target[3];
+  float up[3];
+  float vfov_deg;
+} cloud_camera;
+
+/* Method parameters.
+ *  steps        N primary samples over the ray's chord through the box, at
+ *               t_near + (i + j) * D, D = chord / N (Sections 1 and 3.2).
+ *  light_steps  L samples of the march towards the sun (Section 1), at the
+ *               midpoints of L equal steps to the box exit; 0 disables it.
+ *  alpha        extinction per unit density (the paper's "absorption"), >= 0.
+ *  g            Henyey-Greenstein asymmetry, |g| < 1 (Section 1).
+ *  sun_dir      direction towards the sun (any non-zero length).
+ *  sun_color    light colour times intensity, per channel.
+ *  ambient      ambient light added to the incident light (Section 1).
+ *  jitter       0: j = 0.5 for every ray; 1: per-pixel offset j in [0, 1)
+ *               from the PCG hash chain of (px, py, frame_index, seed)
+ *               (Section 3.2's random per-pixel start offset).
+ *  integration  1: analytic, S += T L_in (1 - exp(-rho alpha D)) (Section 3.1);
+ *               0: the basic rule, T updated first, S += T rho alpha D L_in.
+ *  t_eps        stop a ray once T < t_eps ("until the alpha reaches 1",
+ *               Section 1); 0 disables the early exit. */
+typedef struct {
+  int32_t steps;
+  int32_t light_steps;
+  float alpha;
+  float g;
+  float sun_dir[3];
+  float sun_color[3];
+  float ambient[3];
+  int32_t jitter;
+  uint32_t seed;
+  int32_t integration;
+  float t_eps;
+} cloud_params;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* cloud_last_error(void);
+
+/* CLOUD_ABI_VERSION of the loaded library. */
+int cloud_abi_version(void);
+
+/* Render one frame of the cloud layer (Sections 1, 3.1, 3.2).
+ *  out_rgba   device [height][width][4] float32, written completely (rays
+ *             that miss the box get 0).
+ *  frame_index feeds the jitter hash. width, height >= 1. */
+int cloud_render(const cloud_volume* volume, const cloud_camera* camera,
+                 const cloud_params* params, uint32_t frame_index,
+                 int32_t width, int32_t height, float* out_rgba,
+                 void* hip_stream);
+
+/* Render n_views cameras of one volume in one launch (same size, params and
+ * frame_index). cameras is a host array of n_views; out_rgba is device
+ * [n_views][height][width][4]. View v's pixels hash exactly as in
+ * cloud_render. n_views >= 1. */
+int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras,
+                       int32_t n_views, const cloud_params* params,
+                       uint32_t frame_index, int32_t width, int32_t height,
+                       float* out_rgba, void* hip_stream);
+
+/* March n explicit rays (same method as cloud_render; used to check single
+ * rays against closed forms).
+ *  origins, dirs  device [n][3] float32; dirs are normalised by the library
+ *                 and must be non-zero.
+ *  pixel_xy       device [n][2] uint32 (px, py) fed to the jitter hash, or
+ *                 NULL for j = 0.5; ignored when params->jitter == 0.
+ *  out_rgba       device [n][4] float32. n == 0 is a no-op. */
+int cloud_march_rays(const cloud_volume* volume, const float* origins,
+                     const float* dirs, const uint32_t* pixel_xy, int64_t n,
+                     const cloud_params* params, uint32_t frame_index,
+                     float* out_rgba, void* hip_stream);
+
+/* Temporal resolve of a jittered frame (Section 3.2): for each pixel and
+ * channel, clamp the history into the min/max of the current frame's 3x3
+ * neighbourhood (edges clamped), then out = h + blend * (current - h).
+ * history == NULL or frame_index == 0 copies current to out.
+ *  current, history, out  device [height][width][4] float32.
+ *  out may equal history (in-place update); out must not overlap current.
+ *  0 < blend <= 1. */
+int cloud_taa_resolve(const float* current, const float* history, float* out,
+                      int32_t width, int32_t height, float blend,
+                      uint32_t frame_index, void* hip_stream);
+
+/* Checks that [ptr, ptr + bytes) lies inside one HIP device allocation: the
+ * check every entry point applies to its buffers before launching anything.
+ * Returns CLOUD_OK or CLOUD_E_INVALID (NULL, host memory, or a range that
+ * runs past the end of its allocation). Launches nothing. */
+int cloud_check_buffer(const void* ptr, uint64_t bytes);
+
+/* The per-pixel start offsets the renderer draws (Section 3.2's random
+ * offset), exposed so callers can reproduce a frame's sample positions:
+ * out_bits[i] = j * 2^24 (an integer below 2^24) for pixel
+ * (pixel_xy[2i], pixel_xy[2i+1]) at frame_index and seed.
+ *  pixel_xy device [n][2] uint32; out_bits device [n] uint32; n == 0 is a
+ *  no-op. */
+int cloud_jitter_offsets(const uint32_t* pixel_xy, int64_t n, uint32_t frame_index,
+                         uint32_t seed, uint32_t* out_bits, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLOUD_H */

@@ -1,0 +1,41 @@
+"""MI355X (gfx950) cloud raymarch: the method of "Optimisations for Real-Time
+Volumetric Cloudscapes" (Toft, Bowles and Zimmermann, arXiv 1609.05344) as
+hand-written HIP kernels behind a C ABI (include/cloud.h).
+
+The Python layer is a thin ctypes binding (argument marshalling only); the
+library is loaded on first use and raises if it has not been built.
+"""
+
+from ._lib import (  # noqa: F401
+    CloudError,
+    Volume,
+    cloud_check_buffer,
+    cloud_jitter_offsets,
+    cloud_march_rays,
+    cloud_render,
+    cloud_render_views,
+    cloud_taa_resolve,
+    last_error,
+    load,
+)
+
+
+def device_volume(scene, device="cuda"):
+    """Upload a seeded scene's stored volumes (see scenes.make_scene)."""
+    import numpy as np
+    import torch
+
+    w = scene.workload
+
+    def up(a):
+        if a is None:
+            return None
+        if a.dtype == np.uint16:   # bfloat16 bit patterns
+            return torch.from_numpy(a.view(np.int16)).to(device).view(torch.bfloat16)
+        return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+    base, det = up(scene.base_stored), up(scene.detail_stored)
+    dtype = {np.dtype(np.float32): "f32", np.dtype(np.float16): "f16",
+             np.dtype(np.uint16): "bf16"}[scene.base_stored.dtype]
+    return Volume(base, det, dtype=dtype, detail_weight=w.params.detail_weight,
+                  detail_tiling=w.params.detail_tiling)

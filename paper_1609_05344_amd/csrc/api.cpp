@@ -1,0 +1,341 @@
+// C ABI entry points: argument checks, conversion to launch form, launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "../../include/cloud.h"
+#include "cloud_launch.h"
+#include "cloud_prepare.h"
+
+namespace cloud {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+size_t dtype_size(int dtype) {
+  switch (dtype) {
+    case CLOUD_F32: return 4;
+    case CLOUD_F16: return 2;
+    case CLOUD_BF16: return 2;
+    default: return 0;
+  }
+}
+
+static bool finite3(const float* v) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+int check_span(const void* p, size_t bytes, const char* what) {
+  if (p == nullptr) return fail(CLOUD_E_INVALID, std::string(what) + " is NULL");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && base) {
+    const char* b = static_cast<const char*>(base);
+    const char* q = static_cast<const char*>(p);
+    if (q < b || (size_t)(q - b) + bytes > size) {
+      char buf[256];
+      snprintf(buf, sizeof buf, "%s: %zu bytes at offset %zu exceed its %zu-byte allocation",
+               what, bytes, (size_t)(q - b), size);
+      return fail(CLOUD_E_INVALID, buf);
+    }
+    return CLOUD_OK;
+  }
+  (void)hipGetLastError();
+  return fail(CLOUD_E_INVALID, std::string(what) + " is not inside a device allocation");
+}
+
+int check_image(int W, int H, long long views) {
+  if (W < 1 || H < 1) return fail(CLOUD_E_INVALID, "width and height must be >= 1");
+  if (W > 65536 || H > 65536) return fail(CLOUD_E_INVALID, "width and height must be <= 65536");
+  const long long tiles = (long long)((W + 15) / 16) * ((H + 15) / 16) * views;
+  if (tiles > 0x7FFFFFFFLL) return fail(CLOUD_E_INVALID, "image too large");
+  return CLOUD_OK;
+}
+
+int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
+  if (!v) return fail(CLOUD_E_INVALID, "volume is NULL");
+  if (v->layout != 0) return fail(CLOUD_E_INVALID, "volume layout must be 0 (dense)");
+  if (dtype_size(v->dtype) == 0) return fail(CLOUD_E_INVALID, "unknown volume dtype");
+  if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(CLOUD_E_INVALID, "volume dims must be >= 2");
+  const long long texels = (long long)v->nx * v->ny * v->nz;
+  if (texels > 0x7FFFFFFFLL) return fail(CLOUD_E_INVALID, "volume has more than 2^31-1 texels");
+  for (int k = 0; k < 3; ++k) {
+    if (!std::isfinite(v->box_min[k]) || !std::isfinite(v->box_max[k]) ||
+        !(v->box_max[k] > v->box_min[k]))
+      return fail(CLOUD_E_INVALID, "box_max must exceed box_min on every axis");
+  }
+  int rc = check_span(v->base, (size_t)texels * dtype_size(v->dtype), "volume base");
+  if (rc) return rc;
+  DevVolume d = {};
+  d.base = v->base;
+  d.nx = v->nx; d.ny = v->ny; d.nz = v->nz;
+  const int n[3] = {v->nx, v->ny, v->nz};
+  float* s[3] = {&d.sx, &d.sy, &d.sz};
+  float* o[3] = {&d.ox, &d.oy, &d.oz};
+  for (int k = 0; k < 3; ++k) {
+    const double sc = (double)n[k] / ((double)v->box_max[k] - (double)v->box_min[k]);
+    *s[k] = (float)sc;
+    *o[k] = (float)(-(double)v->box_min[k] * sc - 0.5);
+    d.bmin[k] = v->box_min[k];
+    d.bmax[k] = v->box_max[k];
+  }
+  d.detail = nullptr;
+  if (v->detail) {
+    if (v->ddtype != v->dtype)
+      return fail(CLOUD_E_INVALID, "detail dtype must equal the base dtype");
+    if (v->dnx < 2 || v->dny < 2 || v->dnz < 2)
+      return fail(CLOUD_E_INVALID, "detail dims must be >= 2");
+    const long long dt = (long long)v->dnx * v->dny * v->dnz;
+    if (dt > 0x7FFFFFFFLL) return fail(CLOUD_E_INVALID, "detail volume too large");
+    if (!std::isfinite(v->detail_weight) || v->detail_weight < 0.0f || v->detail_weight >= 1.0f)
+      return fail(CLOUD_E_INVALID, "detail_weight must be in [0, 1)");
+    if (!std::isfinite(v->detail_tiling) || !(v->detail_tiling > 0.0f))
+      return fail(CLOUD_E_INVALID, "detail_tiling must be > 0");
+    rc = check_span(v->detail, (size_t)dt * dtype_size(v->ddtype), "volume detail");
+    if (rc) return rc;
+    d.detail = v->detail;
+    d.dnx = v->dnx; d.dny = v->dny; d.dnz = v->dnz;
+    const int dn[3] = {v->dnx, v->dny, v->dnz};
+    float* ds[3] = {&d.dsx, &d.dsy, &d.dsz};
+    float* dof[3] = {&d.dox, &d.doy, &d.doz};
+    for (int k = 0; k < 3; ++k) {
+      const double sc = (double)dn[k] * (double)v->detail_tiling /
+                        ((double)v->box_max[k] - (double)v->box_min[k]);
+      *ds[k] = (float)sc;
+      *dof[k] = (float)(-(double)v->box_min[k] * sc - 0.5);
+    }
+    d.detail_weight = v->detail_weight;
+  }
+  *out = d;
+  *dtype = v->dtype;
+  return CLOUD_OK;
+}
+
+int prepare_params(const cloud_params* p, const cloud_volume* v, DevParams* out) {
+  if (!p) return fail(CLOUD_E_INVALID, "params is NULL");
+  if (p->steps < 1 || p->steps > (1 << 20)) return fail(CLOUD_E_INVALID, "steps must be in [1, 2^20]");
+  if (p->light_steps < 0 || p->light_steps > 4096)
+    return fail(CLOUD_E_INVALID, "light_steps must be in [0, 4096]");
+  if (!std::isfinite(p->alpha) || p->alpha < 0.0f) return fail(CLOUD_E_INVALID, "alpha must be finite and >= 0");
+  if (!std::isfinite(p->g) || !(std::fabs(p->g) < 1.0f)) return fail(CLOUD_E_INVALID, "|g| must be < 1");
+  if (!finite3(p->sun_dir) || !finite3(p->sun_color) || !finite3(p->ambient))
+    return fail(CLOUD_E_INVALID, "sun_dir, sun_color and ambient must be finite");
+  const double sl = std::sqrt((double)p->sun_dir[0] * p->sun_dir[0] +
+                              (double)p->sun_dir[1] * p->sun_dir[1] +
+                              (double)p->sun_dir[2] * p->sun_dir[2]);
+  if (!(sl > 0.0)) return fail(CLOUD_E_INVALID, "sun_dir must be non-zero");
+  if (p->jitter != 0 && p->jitter != 1) return fail(CLOUD_E_INVALID, "jitter must be 0 or 1");
+  if (p->integration != 0 && p->integration != 1)
+    return fail(CLOUD_E_INVALID, "integration must be 0 (naive) or 1 (analytic)");
+  if (!std::isfinite(p->t_eps) || p->t_eps < 0.0f) return fail(CLOUD_E_INVALID, "t_eps must be finite and >= 0");
+  DevParams d = {};
+  d.steps = p->steps;
+  d.light_steps = p->light_steps;
+  d.alpha = p->alpha;
+  d.alpha_log2e = (float)((double)p->alpha * 1.4426950408889634);
+  d.inv_light_steps = p->light_steps > 0 ? (float)(1.0 / p->light_steps) : 0.0f;
+  for (int k = 0; k < 3; ++k) {
+    const double sk = (double)p->sun_dir[k] / sl;
+    d.s[k] = (float)sk;
+    d.s_axis[k] = d.s[k] != 0.0f;
+    d.inv_s[k] = d.s_axis[k] ? (float)(1.0 / (double)d.s[k]) : 0.0f;
+    d.light_bound[k] = d.s[k] > 0.0f ? v->box_max[k] : v->box_min[k];
+    d.sun[k] = p->sun_color[k];
+    d.amb[k] = p->ambient[k];
+  }
+  const double g = p->g;
+  d.hg_k = (float)((1.0 - g * g) / (4.0 * M_PI));
+  d.hg_a = (float)(1.0 + g * g);
+  d.hg_b = (float)(2.0 * g);
+  d.jitter = p->jitter;
+  d.seed = p->seed;
+  d.integration = p->integration;
+  d.t_eps = p->t_eps;
+  *out = d;
+  return CLOUD_OK;
+}
+
+int prepare_camera(const cloud_camera* c, int W, int H, DevCamera* out) {
+  if (!c) return fail(CLOUD_E_INVALID, "camera is NULL");
+  if (!finite3(c->pos) || !finite3(c->target) || !finite3(c->up) || !std::isfinite(c->vfov_deg))
+    return fail(CLOUD_E_INVALID, "camera values must be finite");
+  if (!(c->vfov_deg > 0.0f && c->vfov_deg < 180.0f))
+    return fail(CLOUD_E_INVALID, "vfov_deg must be in (0, 180)");
+  double f[3], r[3], u[3];
+  for (int k = 0; k < 3; ++k) f[k] = (double)c->target[k] - c->pos[k];
+  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(fl > 0.0)) return fail(CLOUD_E_INVALID, "camera target equals its position");
+  for (double& x : f) x /= fl;
+  const double up[3] = {c->up[0], c->up[1], c->up[2]};
+  r[0] = f[1] * up[2] - f[2] * up[1];
+  r[1] = f[2] * up[0] - f[0] * up[2];
+  r[2] = f[0] * up[1] - f[1] * up[0];
+  const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(rl > 1e-12)) return fail(CLOUD_E_INVALID, "camera up is parallel to the view direction");
+  for (double& x : r) x /= rl;
+  u[0] = r[1] * f[2] - r[2] * f[1];
+  u[1] = r[2] * f[0] - r[0] * f[2];
+  u[2] = r[0] * f[1] - r[1] * f[0];
+  DevCamera d;
+  for (int k = 0; k < 3; ++k) {
+    d.pos[k] = c->pos[k];
+    d.fwd[k] = (float)f[k];
+    d.right[k] = (float)r[k];
+    d.up[k] = (float)u[k];
+  }
+  d.tan_half = (float)std::tan((double)c->vfov_deg * M_PI / 360.0);
+  d.aspect = (float)((double)W / (double)H);
+  *out = d;
+  return CLOUD_OK;
+}
+
+}  // namespace cloud
+
+using namespace cloud;
+
+#define CLOUD_GUARD_BEGIN try {
+#define CLOUD_GUARD_END                                                          \
+  }                                                                              \
+  catch (const std::bad_alloc&) {                                                \
+    return fail(CLOUD_E_NOMEM, "host allocation failed");                        \
+  }                                                                              \
+  catch (...) {                                                                  \
+    return fail(CLOUD_E_INVALID, "internal error");                              \
+  }
+
+extern "C" {
+
+const char* cloud_last_error(void) { return g_last_error.c_str(); }
+
+int cloud_abi_version(void) { return CLOUD_ABI_VERSION; }
+
+int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
+                       const cloud_params* params, uint32_t frame_index, int32_t width,
+                       int32_t height, float* out_rgba, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (!cameras) return fail(CLOUD_E_INVALID, "cameras is NULL");
+  if (n_views < 1) return fail(CLOUD_E_INVALID, "n_views must be >= 1");
+  int rc = check_image(width, height, n_views);
+  if (rc) return rc;
+  DevVolume v;
+  int dtype;
+  if ((rc = prepare_volume(volume, &v, &dtype))) return rc;
+  DevParams p;
+  if ((rc = prepare_params(params, volume, &p))) return rc;
+  if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
+    return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
+  const size_t px = (size_t)width * height;
+  if ((rc = check_span(out_rgba, px * 16 * (size_t)n_views, "out_rgba"))) return rc;
+  DevCameras cams;
+  for (int i = 0; i < n_views; ++i) {
+    if ((rc = prepare_camera(&cameras[i], width, height, &cams.c[i % kMaxViews]))) return rc;
+    const bool last = i + 1 == n_views;
+    if ((i + 1) % kMaxViews == 0 || last) {
+      const int first = i - i % kMaxViews;
+      const int count = i - first + 1;
+      hipError_t e = launch_render(v, dtype, p, cams, count, frame_index, width, height,
+                                   out_rgba + (size_t)first * px * 4,
+                                   static_cast<hipStream_t>(hip_stream));
+      if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("render launch: ") + hipGetErrorString(e));
+    }
+  }
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_render(const cloud_volume* volume, const cloud_camera* camera,
+                 const cloud_params* params, uint32_t frame_index, int32_t width, int32_t height,
+                 float* out_rgba, void* hip_stream) {
+  if (!camera) return fail(CLOUD_E_INVALID, "camera is NULL");
+  return cloud_render_views(volume, camera, 1, params, frame_index, width, height, out_rgba,
+                            hip_stream);
+}
+
+int cloud_march_rays(const cloud_volume* volume, const float* origins, const float* dirs,
+                     const uint32_t* pixel_xy, int64_t n, const cloud_params* params,
+                     uint32_t frame_index, float* out_rgba, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (n < 0) return fail(CLOUD_E_INVALID, "n must be >= 0");
+  if (n > (int64_t)1 << 31) return fail(CLOUD_E_INVALID, "n must be <= 2^31");
+  DevVolume v;
+  int dtype, rc;
+  if ((rc = prepare_volume(volume, &v, &dtype))) return rc;
+  DevParams p;
+  if ((rc = prepare_params(params, volume, &p))) return rc;
+  if (n == 0) return CLOUD_OK;
+  if ((rc = check_span(origins, (size_t)n * 12, "origins"))) return rc;
+  if ((rc = check_span(dirs, (size_t)n * 12, "dirs"))) return rc;
+  if (pixel_xy && (rc = check_span(pixel_xy, (size_t)n * 8, "pixel_xy"))) return rc;
+  if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
+    return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
+  if ((rc = check_span(out_rgba, (size_t)n * 16, "out_rgba"))) return rc;
+  hipError_t e = launch_rays(v, dtype, p, frame_index, origins, dirs, pixel_xy, n, out_rgba,
+                             static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("march launch: ") + hipGetErrorString(e));
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_taa_resolve(const float* current, const float* history, float* out, int32_t width,
+                      int32_t height, float blend, uint32_t frame_index, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  int rc = check_image(width, height, 1);
+  if (rc) return rc;
+  if (!std::isfinite(blend) || !(blend > 0.0f) || blend > 1.0f)
+    return fail(CLOUD_E_INVALID, "blend must be in (0, 1]");
+  const size_t bytes = (size_t)width * height * 16;
+  if ((rc = check_span(current, bytes, "current"))) return rc;
+  if ((rc = check_span(out, bytes, "out"))) return rc;
+  const bool copy = history == nullptr || frame_index == 0;
+  if (!copy && (rc = check_span(history, bytes, "history"))) return rc;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(current), b = reinterpret_cast<uintptr_t>(out);
+  if ((a | b | reinterpret_cast<uintptr_t>(history)) % 16)
+    return fail(CLOUD_E_INVALID, "images must be 16-byte aligned");
+  if (a < b + bytes && b < a + bytes) return fail(CLOUD_E_INVALID, "out overlaps current");
+  if (!copy && history != out) {
+    const uintptr_t h = reinterpret_cast<uintptr_t>(history);
+    if (h < b + bytes && b < h + bytes)
+      return fail(CLOUD_E_INVALID, "out partially overlaps history");
+  }
+  hipError_t e = launch_taa(current, history, out, width, height, blend, copy,
+                            static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_check_buffer(const void* ptr, uint64_t bytes) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  return check_span(ptr, (size_t)bytes, "buffer");
+  CLOUD_GUARD_END
+}
+
+int cloud_jitter_offsets(const uint32_t* pixel_xy, int64_t n, uint32_t frame_index, uint32_t seed,
+                         uint32_t* out_bits, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (n < 0 || n > (int64_t)1 << 31) return fail(CLOUD_E_INVALID, "n must be in [0, 2^31]");
+  if (n == 0) return CLOUD_OK;
+  int rc;
+  if ((rc = check_span(pixel_xy, (size_t)n * 8, "pixel_xy"))) return rc;
+  if ((rc = check_span(out_bits, (size_t)n * 4, "out_bits"))) return rc;
+  hipError_t e = launch_jitter(pixel_xy, n, frame_index, seed, out_bits,
+                               static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("jitter launch: ") + hipGetErrorString(e));
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,27 @@
+// Host-side launchers of the kernels (argument checks happen before these).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cloud_types.h"
+
+namespace cloud {
+
+// Render n_views (<= kMaxViews) cameras into out [n_views][H][W][4].
+hipError_t launch_render(const DevVolume& v, int dtype, const DevParams& p, const DevCameras& c,
+                         int n_views, uint32_t frame, int W, int H, float* out, hipStream_t s);
+
+// March n explicit rays into out [n][4].
+hipError_t launch_rays(const DevVolume& v, int dtype, const DevParams& p, uint32_t frame,
+                       const float* o, const float* d, const uint32_t* pxy, long long n,
+                       float* out, hipStream_t s);
+
+// Jitter offsets (as integers j * 2^24) of n pixels.
+hipError_t launch_jitter(const uint32_t* pxy, long long n, uint32_t frame, uint32_t seed,
+                         uint32_t* out, hipStream_t s);
+
+// Temporal resolve, or a plain copy of cur when copy is set.
+hipError_t launch_taa(const float* cur, const float* hist, float* out, int W, int H, float blend,
+                      bool copy, hipStream_t s);
+
+}  // namespace cloud

@@ -1,0 +1,56 @@
+// Launch-ready forms of the ABI structs (host and device).
+//
+// The host side folds everything that is uniform over a launch -- texel
+// scaling, the normalised sun direction, light-exit planes, phase constants,
+// the camera basis -- into these structs once per call, so the kernels do no
+// per-pixel set-up beyond the ray itself.
+#pragma once
+
+#include <stdint.h>
+
+namespace cloud {
+
+constexpr int kMaxViews = 16;   // cameras carried by value in one launch
+
+struct DevVolume {
+  const void* base;
+  int nx, ny, nz;
+  // continuous texel coordinate along each axis: f = p * s + o, texel k's
+  // centre at f = k (texel centres at box_min + (k + 0.5) * extent / n)
+  float sx, sy, sz, ox, oy, oz;
+  const void* detail;
+  int dnx, dny, dnz;
+  float dsx, dsy, dsz, dox, doy, doz;
+  float detail_weight;
+  float bmin[3], bmax[3];
+};
+
+struct DevParams {
+  int steps, light_steps;
+  float alpha;          // extinction per unit density
+  float alpha_log2e;    // alpha * log2(e), for exp2
+  float inv_light_steps;
+  float s[3];           // unit direction towards the sun
+  float light_bound[3]; // exit plane per axis along s (box_max if s_k > 0)
+  float inv_s[3];       // 1 / s_k
+  int s_axis[3];        // s_k != 0
+  float sun[3], amb[3];
+  float hg_k;           // (1 - g^2) / (4 pi)
+  float hg_a, hg_b;     // 1 + g^2, 2 g
+  int jitter;
+  uint32_t seed;
+  int integration;
+  float t_eps;
+};
+
+struct DevCamera {
+  float pos[3];
+  float fwd[3], right[3], up[3];
+  float tan_half, aspect;   // tan(vfov/2), width/height
+};
+
+struct DevCameras {
+  DevCamera c[kMaxViews];
+};
+
+}  // namespace cloud

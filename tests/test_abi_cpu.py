@@ -1,0 +1,86 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/*.h, its structs have the layout the binding assumes, and
+argument errors that precede any device call are reported as documented."""
+
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1609_05344_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1609_05344_amd.build import build
+        build()
+    return _lib.load()
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^[A-Za-z_][\w \t\*]*?\b(cloud_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 6
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert lib.cloud_abi_version() == 1
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sizes.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "cloud.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(cloud_volume),"
+        " sizeof(cloud_camera), sizeof(cloud_params), offsetof(cloud_volume, layout),"
+        " offsetof(cloud_params, t_eps), offsetof(cloud_volume, detail));return 0;}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got == [ctypes.sizeof(_lib.cloud_volume), ctypes.sizeof(_lib.cloud_camera),
+                   ctypes.sizeof(_lib.cloud_params), _lib.cloud_volume.layout.offset,
+                   _lib.cloud_params.t_eps.offset, _lib.cloud_volume.detail.offset]
+
+
+def test_argument_errors_before_any_launch(lib):
+    cam = _lib.cloud_camera()
+    prm = _lib.cloud_params()
+    rc = lib.cloud_render(None, ctypes.byref(cam), ctypes.byref(prm), 0, 8, 8, None, None)
+    assert rc == _lib.CLOUD_E_INVALID and "volume is NULL" in _lib.last_error()
+    vol = _lib.cloud_volume()
+    rc = lib.cloud_render(ctypes.byref(vol), None, ctypes.byref(prm), 0, 8, 8, None, None)
+    assert rc == _lib.CLOUD_E_INVALID and "camera" in _lib.last_error()
+    rc = lib.cloud_render(ctypes.byref(vol), ctypes.byref(cam), ctypes.byref(prm), 0, 0, 8, None, None)
+    assert rc == _lib.CLOUD_E_INVALID and "width" in _lib.last_error()
+    vol.dtype = 7
+    rc = lib.cloud_render(ctypes.byref(vol), ctypes.byref(cam), ctypes.byref(prm), 0, 8, 8, None, None)
+    assert rc == _lib.CLOUD_E_INVALID and "dtype" in _lib.last_error()
+    vol.dtype, vol.layout = 0, 3
+    rc = lib.cloud_render(ctypes.byref(vol), ctypes.byref(cam), ctypes.byref(prm), 0, 8, 8, None, None)
+    assert rc == _lib.CLOUD_E_INVALID and "layout" in _lib.last_error()
+    rc = lib.cloud_taa_resolve(None, None, None, 8, 8, 1.5, 1, None)
+    assert rc == _lib.CLOUD_E_INVALID and "blend" in _lib.last_error()
+    rc = lib.cloud_taa_resolve(None, None, None, 8, -1, 0.1, 1, None)
+    assert rc == _lib.CLOUD_E_INVALID
+    rc = lib.cloud_march_rays(ctypes.byref(vol), None, None, None, -1, ctypes.byref(prm), 0, None, None)
+    assert rc == _lib.CLOUD_E_INVALID
+    rc = lib.cloud_render_views(ctypes.byref(vol), ctypes.byref(cam), 0, ctypes.byref(prm), 0, 8, 8,
+                                None, None)
+    assert rc == _lib.CLOUD_E_INVALID and "n_views" in _lib.last_error()
+    # a successful-looking call leaves the error text of the last failure only
+    assert lib.cloud_jitter_offsets(None, 0, 0, 0, None, None) == _lib.CLOUD_OK

@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the cloud raymarch hot path on one MI355X.
+
+One step = one frame of the whole hot path at 1920x1080: per-pixel primary
+march with a jittered start (8 steps), a 6-step light march per sample, phase
+plus ambient, analytic step integration (one render launch), then the
+3x3-clamped temporal resolve into the history (one resolve launch). The
+camera orbits one degree per frame, as in the paper's moving-scene use.
+
+    python bench.py [--gpus 1] [--steps 60] [--warmup 10]
+
+Prints one JSON line. `value` is executed trilinear density lookups per
+second (Gsamples/s) over the timed frames, inputs resident in HBM; the
+per-frame lookup count comes from the library's own counter (not timed).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_HBM_GBPS = 8000.0
+MI355X_FP32_VECTOR_TFLOPS = 157.3
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle as it stands, over row bands, all host cores
+# ---------------------------------------------------------------------------
+
+def _oracle_band(args):
+    name, dtype, frame, y0, y1 = args
+    import numpy as np
+    from oracle import cloud as O
+    from paper_1609_05344_amd import scenes
+    w = scenes.workload(name)
+    sc = scenes.make_scene(w, dtype=dtype)
+    vol = O.OracleVolume(base=sc.base_f64)
+    ys, xs = np.meshgrid(np.arange(y0, y1), np.arange(w.width), indexing="ij")
+    pix = np.stack([xs.reshape(-1), ys.reshape(-1)], 1)
+    t = time.perf_counter()
+    _, lk = O.render(vol, w.camera(frame), w.params, w.width, w.height, frame=frame, pixels=pix,
+                     return_lookups=True)
+    return lk, time.perf_counter() - t
+
+
+def cpu_baseline(name: str, dtype: str, frames: int, cores: int) -> dict:
+    from paper_1609_05344_amd import scenes
+    w = scenes.workload(name)
+    scenes.make_scene(w, dtype=dtype)          # generate/cache the volume once
+    bands = cores * 4
+    edges = [round(i * w.height / bands) for i in range(bands + 1)]
+    jobs = [(name, dtype, f, edges[b], edges[b + 1]) for f in range(frames) for b in range(bands)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_band, jobs[:cores])     # warm the workers (imports, volume load)
+        t = time.perf_counter()
+        res = pool.map(_oracle_band, jobs)
+        dt = time.perf_counter() - t
+    lookups = sum(r[0] for r in res)
+    return {"value": round(lookups / dt / 1e9, 6), "unit": "Gsamples/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{frames} full {w.width}x{w.height} frames of the same workload "
+                      f"({lookups} executed lookups, {dt:.1f} s wall), FP64 numpy, "
+                      f"{cores} processes over row bands",
+            "ms_per_frame": round(dt * 1e3 / frames, 1)}
+
+
+# ---------------------------------------------------------------------------
+# Served form: many camera streams through cloud_serve_* (closed loop)
+# ---------------------------------------------------------------------------
+
+def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams: int,
+                       seconds: float, warm_s: float = 0.5) -> dict:
+    """n_streams streams of the workload, each submitting its next frame as
+    soon as the previous one completes; frames/s and frame latency
+    (submit -> done) over the measured window."""
+    import numpy as np
+    sc = scenes.make_scene(w, dtype=dtype)
+    vol = cf.device_volume(sc)
+    if layout != "dense":
+        vol = cf.cloud_volume_pack(vol, layout)
+    W, H = w.width, w.height
+    outs = [torch.empty((H, W, 4), device="cuda") for _ in range(n_streams)]
+    frame = [0] * n_streams
+    lat, done_t = [], []
+    with cf.Server(vol, budget_bytes=n_streams * W * H * 40, max_batch=64) as srv:
+        t_start = time.monotonic()
+        for s in range(n_streams):
+            srv.submit(s, w.camera(0, view=s % 8), w.params, W, H, 0, outs[s])
+        t_end = t_start + warm_s + seconds
+        while time.monotonic() < t_end:
+            got = srv.poll(256)
+            if not got:
+                srv.wait(0.002)
+                continue
+            for c in got:
+                assert c["status"] == 0, c
+                s = c["stream_id"]
+                if c["t_done_ns"] * 1e-9 >= t_start + warm_s:
+                    lat.append((c["t_done_ns"] - c["t_submit_ns"]) * 1e-6)
+                    done_t.append(c["t_done_ns"] * 1e-9)
+                frame[s] += 1
+                srv.submit(s, w.camera(frame[s], view=s % 8), w.params, W, H, frame[s], outs[s])
+        st = srv.stats()
+    done_t.sort()
+    span = done_t[-1] - done_t[0] if len(done_t) > 1 else float("nan")
+    fps = (len(done_t) - 1) / span if len(done_t) > 1 else 0.0
+    return {"form": f"served, {dtype} storage, {layout} layout", "streams": n_streams,
+            "frames_per_s": round(fps, 1), "ms_per_frame": round(1e3 / fps, 4) if fps else None,
+            "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "latency_p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "frames": len(lat), "batches": st["batches"]}
+
+
+# ---------------------------------------------------------------------------
+# GPU run
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="H")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--layout", default="quad", choices=["dense", "quad", "oct"])
+    ap.add_argument("--served-streams", type=int, default=64)
+    ap.add_argument("--served-seconds", type=float, default=2.0)
+    ap.add_argument("--served-dtype", default="f16", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--served-layout", default="oct", choices=["dense", "quad", "oct"])
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=36)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="launch one plain copy of this many MiB first (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(frames and streams are independent; see the sharding notes in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cores = min(os.cpu_count() or 1, 16)
+        cpu = cpu_baseline(args.workload, args.dtype, args.cpu_frames, cores)
+
+    import numpy as np
+    import torch
+
+    import paper_1609_05344_amd as cf
+    from paper_1609_05344_amd import scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = scenes.workload(args.workload)
+    sc = scenes.make_scene(w, dtype=args.dtype)
+    vol = cf.device_volume(sc, dev)
+    if args.layout != "dense":
+        vol = cf.cloud_volume_pack(vol, args.layout)
+    W, H, p = w.width, w.height, w.params
+    total = args.warmup + args.steps
+
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # executed lookups per frame (library counter, outside the timed region)
+    counts = torch.zeros((total,), dtype=torch.int64, device=dev)
+    for f in range(total):
+        cf.cloud_count_lookups(vol, w.camera(f), p, f, W, H, out=counts[f:f + 1])
+    counts = counts.cpu().numpy()
+
+    cur = torch.empty((H, W, 4), device=dev)
+    hist = torch.zeros((H, W, 4), device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+
+    def frame(f, events=None):
+        if events:
+            events[0].record()
+        cf.cloud_render(vol, w.camera(f), p, f, W, H, out=cur)
+        if events:
+            events[1].record()
+        cf.cloud_taa_resolve(cur, hist, hist, w.taa_blend, f)
+
+    for f in range(args.warmup):
+        frame(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        frame(args.warmup + k, ev[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    render_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    lk_timed = int(counts[args.warmup:].sum())
+    lk_frame = lk_timed / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    value = lk_timed / wall / 1e9
+
+    elem = 4 if args.dtype == "f32" else 2
+    bytes_per_lookup = 8 * elem
+    achieved = lk_frame * bytes_per_lookup / (render_ms * 1e-3) / 1e9
+    line = {
+        "metric": "Gsamples/s @1080p 8-step+TAA (executed trilinear density lookups per second; "
+                  "ms/frame in ms_per_step)",
+        "value": round(value, 3),
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded 5-octave value-noise FBM density 256^3 "
+                f"({args.dtype} storage, {args.layout} layout), orbiting camera",
+        "config": {"workload": f"{w.name}: {w.description}", "width": W, "height": H,
+                   "primary_steps": p.steps, "light_steps": p.light_steps, "jitter": "per-pixel",
+                   "integration": "analytic", "taa_blend": w.taa_blend,
+                   "volume": f"{w.volume.n}^3 {args.dtype}", "layout": args.layout,
+                   "lookups_per_frame": round(lk_frame)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": MI355X_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / MI355X_HBM_GBPS, 4),
+                     "traffic": None, "kernel": "render_kernel",
+                     "kernel_ms": round(render_ms, 4),
+                     "bytes_per_lookup": bytes_per_lookup},
+        "cpu_baseline": cpu,
+    }
+    if not args.no_served:
+        del cur, hist, vol
+        torch.cuda.empty_cache()
+        served = served_closed_loop(cf, scenes, torch, w, args.served_dtype, args.served_layout,
+                                    args.served_streams, args.served_seconds)
+        served["plain_frames_per_s"] = round(1e3 / ms_per_step, 1)
+        served["speedup_vs_plain"] = round(served["frames_per_s"] * ms_per_step / 1e3, 3)
+        line["served"] = served
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -52,6 +52,18 @@ enum {
   CLOUD_E_CANCELLED = -6  /* request dropped by cloud_serve_destroy */
 };
 
+/* Memory layout of a base density volume. Every layout holds the same
+ * texel values and gives bitwise-identical renders; the packed layouts
+ * replicate each trilinear footprint so that a lookup is one or two aligned
+ * fetches instead of eight scattered ones (see cloud_volume_pack).
+ *  DENSE  [nz][ny][nx] texels.
+ *  QUAD   [nz][ny+1][nx+1] entries of 4 texels: entry (z, y', x') holds the
+ *         texels (x, y), (x+1, y), (x, y+1), (x+1, y+1) of plane z with
+ *         x = x'-1, y = y'-1, indices clamped to the volume (4x storage).
+ *  OCT    [nz+1][ny+1][nx+1] entries of 8 texels: the QUAD entry of plane
+ *         z'-1 then that of plane z' (planes clamped; 8x storage). */
+enum { CLOUD_LAYOUT_DENSE = 0, CLOUD_LAYOUT_QUAD = 1, CLOUD_LAYOUT_OCT = 2 };
+
 /* Storage type of a density volume. Every type is decoded exactly to
  * float32; all optical depth, transmittance, exponentials and colour are
  * accumulated in float32. */
@@ -65,10 +77,13 @@ enum { CLOUD_F32 = 0, CLOUD_F16 = 1, CLOUD_BF16 = 2 };
  *          tiled detail_tiling times across the box with repeat addressing.
  *          With detail the density is
  *          clamp((b - detail_weight*d) / (1 - detail_weight*d), 0, 1).
- *  Requirements: n* >= 2, dn* >= 2 when detail is set, box_max > box_min on
- *  every axis, 0 <= detail_weight < 1, detail_tiling > 0, values in [0, 1]
- *  for detail. The volume must stay valid until the call's work has run.
- *  layout must be 0 (dense [nz][ny][nx]). */
+ *  layout  CLOUD_LAYOUT_* of base (a packed base is 16-byte aligned and
+ *          normally made by cloud_volume_pack); nx, ny, nz always count
+ *          texels. The detail volume is always dense.
+ *  Requirements: n* >= 2, dn* >= 2 when detail is set, fewer than 2^24
+ *  entries per plane, box_max > box_min on every axis,
+ *  0 <= detail_weight < 1, detail_tiling > 0, detail values in [0, 1].
+ *  The volume must stay valid until the call's work has run. */
 typedef struct {
   const void* base;
   int32_t nx, ny, nz;
@@ -171,6 +186,35 @@ int cloud_taa_resolve(const float* current, const float* history, float* out,
                       int32_t width, int32_t height, float blend,
                       uint32_t frame_index, void* hip_stream);
 
+/* Adds to *out_count (device, one uint64, 8-byte aligned) the number of
+ * trilinear density lookups cloud_render performs for this frame: one per
+ * primary sample taken plus light_steps per sample with non-zero density,
+ * up to each ray's early exit. Writes no image. Used to report executed
+ * samples per second. */
+int cloud_count_lookups(const cloud_volume* volume, const cloud_camera* camera,
+                        const cloud_params* params, uint32_t frame_index,
+                        int32_t width, int32_t height, uint64_t* out_count,
+                        void* hip_stream);
+
+/* Device bytes a copy of the dense volume's base needs in `layout`. */
+int cloud_volume_packed_bytes(const cloud_volume* dense, int32_t layout,
+                              uint64_t* bytes);
+
+/* Enqueues the repacking of dense->base (layout CLOUD_LAYOUT_DENSE) into dst
+ * in layout CLOUD_LAYOUT_QUAD or CLOUD_LAYOUT_OCT, and fills *packed with
+ * dense's descriptor re-pointed at dst. dst: device, caller-owned,
+ * 16-byte aligned, at least cloud_volume_packed_bytes bytes (dst_bytes), not
+ * overlapping the source. Values are copied bit for bit, so renders of the
+ * packed and dense volumes are identical. */
+int cloud_volume_pack(const cloud_volume* dense, int32_t layout, void* dst,
+                      uint64_t dst_bytes, cloud_volume* packed, void* hip_stream);
+
+/* Launch-shape knob, process-wide, for tuning and benchmarking; results do
+ * not depend on it. Keys: "supertile" (0..64, default 4) -- the render walks
+ * its 16x16-pixel tiles in S x S super-tiles so that the tiles an XCD works on
+ * together cover a compact patch of the image (0 = row-major). */
+int cloud_tune(const char* key, int32_t value);
+
 /* Checks that [ptr, ptr + bytes) lies inside one HIP device allocation: the
  * check every entry point applies to its buffers before launching anything.
  * Returns CLOUD_OK or CLOUD_E_INVALID (NULL, host memory, or a range that
@@ -185,6 +229,92 @@ int cloud_check_buffer(const void* ptr, uint64_t bytes);
  *  no-op. */
 int cloud_jitter_offsets(const uint32_t* pixel_xy, int64_t n, uint32_t frame_index,
                          uint32_t seed, uint32_t* out_bits, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of render requests from many camera streams
+ * (each request is one jittered frame of Section 3.2 plus its temporal
+ * resolve against the stream's history).
+ *
+ * A server shares one volume between all streams. cloud_serve_submit queues
+ * a request and returns at once; a scheduler thread admits queued requests
+ * into batches as batch slots and device memory allow, and runs each batch as
+ * one persistent render launch plus one batched resolve launch (replayed from
+ * a captured HIP graph). Up to two batches are in flight, so requests that
+ * arrive while the device works are admitted into the next batch. A stream has
+ * at most one request in flight (its frames chain through the history);
+ * requests of different streams overlap. Results are bitwise identical to
+ * cloud_render followed by cloud_taa_resolve on the same inputs, whatever
+ * else is in the batch.
+ *
+ * Stream state (the history plus a scratch frame, 2 x width x height x 16
+ * bytes) is library-owned: allocated when the stream's first request is
+ * admitted, counted against hbm_budget_bytes, freed by
+ * cloud_serve_close_stream or cloud_serve_destroy. A stream's resolution is
+ * fixed by its first request. frame_index 0 (or a stream without valid
+ * history) copies the rendered frame instead of resolving it.
+ *
+ * Thread safety: submit, poll, wait and stats may be called from any thread
+ * concurrently; create, close_stream and destroy must not race with other
+ * calls on the same server. Timestamps are CLOCK_MONOTONIC nanoseconds.
+ * ------------------------------------------------------------------------ */
+
+typedef struct cloud_server cloud_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes;  /* device memory for stream state */
+  int32_t max_batch;          /* requests per batch, 1..64 */
+  int32_t max_queue;          /* queued (not yet admitted) requests, >= 1 */
+  int32_t device;             /* HIP device ordinal */
+  float taa_blend;            /* resolve blend, (0, 1] */
+  int32_t use_graphs;         /* 1: replay captured graphs; 0: plain launches */
+} cloud_serve_config;
+
+typedef struct {
+  uint64_t queued, admitted, running, completed, rejected, cancelled, failed;
+  uint64_t streams, bytes_in_use, batches;
+} cloud_serve_stats_t;
+
+typedef struct {
+  uint64_t request_id, stream_id;
+  int32_t status;     /* CLOUD_OK, CLOUD_E_CANCELLED, CLOUD_E_HIP, CLOUD_E_NOMEM */
+  int32_t reserved;
+  int64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns;
+} cloud_completion;
+
+/* Creates a server on cfg->device sharing `shared` (device memory that must
+ * outlive the server; any layout and dtype). */
+int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg,
+                       cloud_server** out);
+
+/* Queues one frame of stream stream_id. out_rgba: device [height][width][4]
+ * float32, caller-owned, 16-byte aligned, not touched by the caller until
+ * the request completes. Returns CLOUD_E_BUSY when the queue is full (retry
+ * later), CLOUD_E_NOMEM when this stream's state can never fit the budget,
+ * CLOUD_E_INVALID for bad arguments or a resolution that differs from the
+ * stream's first request. Camera and params are copied. */
+int cloud_serve_submit(cloud_server* server, uint64_t stream_id,
+                       const cloud_camera* camera, const cloud_params* params,
+                       int32_t width, int32_t height, uint32_t frame_index,
+                       float* out_rgba, uint64_t* request_id);
+
+/* Moves up to max finished requests into out (host array); *n_out gets the
+ * count. Never blocks. */
+int cloud_serve_poll(cloud_server* server, cloud_completion* out, int32_t max,
+                     int32_t* n_out);
+
+/* Blocks until at least one completion can be polled or timeout_ns passes.
+ * Returns 1 if completions are ready, 0 on timeout, or a CLOUD_E_* code. */
+int cloud_serve_wait(cloud_server* server, int64_t timeout_ns);
+
+int cloud_serve_stats(cloud_server* server, cloud_serve_stats_t* out);
+
+/* Cancels the stream's queued requests (they complete as CLOUD_E_CANCELLED)
+ * and frees its state once its in-flight request, if any, has finished.
+ * CLOUD_E_NOTFOUND for an unknown stream. */
+int cloud_serve_close_stream(cloud_server* server, uint64_t stream_id);
+
+/* Cancels queued requests, waits for in-flight batches, frees everything. */
+int cloud_serve_destroy(cloud_server* server);
 
 #ifdef __cplusplus
 }

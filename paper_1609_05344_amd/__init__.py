@@ -8,13 +8,18 @@ library is loaded on first use and raises if it has not been built.
 
 from ._lib import (  # noqa: F401
     CloudError,
+    Server,
     Volume,
     cloud_check_buffer,
+    cloud_count_lookups,
     cloud_jitter_offsets,
     cloud_march_rays,
     cloud_render,
     cloud_render_views,
     cloud_taa_resolve,
+    cloud_tune,
+    cloud_volume_pack,
+    cloud_volume_packed_bytes,
     last_error,
     load,
 )

@@ -23,6 +23,7 @@ CLOUD_E_BUSY = -4
 CLOUD_E_NOTFOUND = -5
 CLOUD_E_CANCELLED = -6
 CLOUD_F32, CLOUD_F16, CLOUD_BF16 = 0, 1, 2
+LAYOUTS = {"dense": 0, "quad": 1, "oct": 2}
 DTYPES = {"f32": CLOUD_F32, "f16": CLOUD_F16, "bf16": CLOUD_BF16}
 
 
@@ -79,8 +80,16 @@ def load():
                                       c_uint32, c_void_p]
     lib.cloud_jitter_offsets.argtypes = [c_void_p, c_int64, c_uint32, c_uint32, c_void_p, c_void_p]
     lib.cloud_check_buffer.argtypes = [c_void_p, c_uint64]
+    lib.cloud_tune.argtypes = [c_char_p, c_int32]
+    lib.cloud_count_lookups.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera),
+                                        POINTER(cloud_params), c_uint32, c_int32, c_int32,
+                                        c_void_p, c_void_p]
+    lib.cloud_volume_packed_bytes.argtypes = [POINTER(cloud_volume), c_int32, POINTER(c_uint64)]
+    lib.cloud_volume_pack.argtypes = [POINTER(cloud_volume), c_int32, c_void_p, c_uint64,
+                                      POINTER(cloud_volume), c_void_p]
     for name in ("cloud_render", "cloud_render_views", "cloud_march_rays", "cloud_taa_resolve",
-                 "cloud_jitter_offsets", "cloud_check_buffer"):
+                 "cloud_jitter_offsets", "cloud_check_buffer", "cloud_count_lookups",
+                 "cloud_volume_packed_bytes", "cloud_volume_pack", "cloud_tune"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -211,6 +220,47 @@ def cloud_march_rays(volume: Volume, origins, dirs, pixel_xy, params, frame_inde
     return out
 
 
+def cloud_count_lookups(volume: Volume, camera, params, frame_index: int, width: int,
+                        height: int, out=None, stream=None):
+    """Density lookups a render of this frame performs (device int64 tensor [1],
+    accumulated into `out` when given)."""
+    import torch
+    if out is None:
+        out = torch.zeros((1,), dtype=torch.int64, device=volume.base.device)
+    cam, prm = make_camera(camera), make_params(params)
+    check(load().cloud_count_lookups(ctypes.byref(volume.struct), ctypes.byref(cam),
+                                     ctypes.byref(prm), int(frame_index) & 0xFFFFFFFF, int(width),
+                                     int(height), _ptr(out), _stream(stream)))
+    return out
+
+
+def cloud_volume_packed_bytes(volume: Volume, layout: str) -> int:
+    n = c_uint64(0)
+    check(load().cloud_volume_packed_bytes(ctypes.byref(volume.struct), LAYOUTS[layout],
+                                           ctypes.byref(n)))
+    return int(n.value)
+
+
+def cloud_volume_pack(volume: Volume, layout: str, stream=None) -> "Volume":
+    """Packed copy of a dense volume (a new device buffer owned by the returned
+    Volume)."""
+    import torch
+    nbytes = cloud_volume_packed_bytes(volume, layout)
+    buf = torch.empty((nbytes,), dtype=torch.uint8, device=volume.base.device)
+    packed = cloud_volume()
+    check(load().cloud_volume_pack(ctypes.byref(volume.struct), LAYOUTS[layout], _ptr(buf), nbytes,
+                                   ctypes.byref(packed), _stream(stream)))
+    out = Volume.__new__(Volume)
+    out.base, out.detail, out.dtype = buf, volume.detail, volume.dtype
+    out.dense = volume
+    out.struct = packed
+    return out
+
+
+def cloud_tune(key: str, value: int) -> None:
+    check(load().cloud_tune(key.encode(), int(value)))
+
+
 def cloud_check_buffer(ptr, nbytes: int) -> int:
     """CLOUD_OK if [ptr, ptr + nbytes) lies inside one device allocation."""
     return load().cloud_check_buffer(_ptr(ptr), int(nbytes))
@@ -233,3 +283,134 @@ def cloud_taa_resolve(current, history, out, blend: float, frame_index: int, str
     check(load().cloud_taa_resolve(_ptr(current), _ptr(history), _ptr(out), width, height,
                                    float(blend), int(frame_index) & 0xFFFFFFFF, _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+class cloud_serve_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", c_uint64), ("max_batch", c_int32), ("max_queue", c_int32),
+                ("device", c_int32), ("taa_blend", c_float), ("use_graphs", c_int32)]
+
+
+class cloud_serve_stats_t(ctypes.Structure):
+    _fields_ = [(n, c_uint64) for n in ("queued", "admitted", "running", "completed", "rejected",
+                                        "cancelled", "failed", "streams", "bytes_in_use",
+                                        "batches")]
+
+
+class cloud_completion(ctypes.Structure):
+    _fields_ = [("request_id", c_uint64), ("stream_id", c_uint64), ("status", c_int32),
+                ("reserved", c_int32), ("t_submit_ns", c_int64), ("t_admit_ns", c_int64),
+                ("t_start_ns", c_int64), ("t_done_ns", c_int64)]
+
+
+def _bind_serve(lib):
+    if getattr(lib, "_serve_bound", False):
+        return lib
+    lib.cloud_serve_create.argtypes = [POINTER(cloud_volume), POINTER(cloud_serve_config),
+                                       POINTER(c_void_p)]
+    lib.cloud_serve_submit.argtypes = [c_void_p, c_uint64, POINTER(cloud_camera),
+                                       POINTER(cloud_params), c_int32, c_int32, c_uint32, c_void_p,
+                                       POINTER(c_uint64)]
+    lib.cloud_serve_poll.argtypes = [c_void_p, POINTER(cloud_completion), c_int32, POINTER(c_int32)]
+    lib.cloud_serve_wait.argtypes = [c_void_p, c_int64]
+    lib.cloud_serve_stats.argtypes = [c_void_p, POINTER(cloud_serve_stats_t)]
+    lib.cloud_serve_close_stream.argtypes = [c_void_p, c_uint64]
+    lib.cloud_serve_destroy.argtypes = [c_void_p]
+    for n in ("cloud_serve_create", "cloud_serve_submit", "cloud_serve_poll", "cloud_serve_wait",
+              "cloud_serve_stats", "cloud_serve_close_stream", "cloud_serve_destroy"):
+        getattr(lib, n).restype = c_int
+    lib._serve_bound = True
+    return lib
+
+
+class Server:
+    """cloud_serve_* over one shared Volume. Keeps the Volume alive."""
+
+    def __init__(self, volume: Volume, budget_bytes: int = 64 << 30, max_batch: int = 64,
+                 max_queue: int = 1024, device: int = 0, taa_blend: float = 0.1,
+                 use_graphs: bool = True):
+        self.lib = _bind_serve(load())
+        self.volume = volume
+        cfg = cloud_serve_config(int(budget_bytes), int(max_batch), int(max_queue), int(device),
+                                 float(taa_blend), 1 if use_graphs else 0)
+        h = c_void_p()
+        check(self.lib.cloud_serve_create(ctypes.byref(volume.struct), ctypes.byref(cfg),
+                                          ctypes.byref(h)))
+        self.handle = h
+
+    def cloud_serve_submit(self, stream_id: int, camera, params, width: int, height: int,
+                           frame_index: int, out) -> int:
+        rid = c_uint64(0)
+        cam, prm = make_camera(camera), make_params(params)
+        rc = self.lib.cloud_serve_submit(self.handle, int(stream_id), ctypes.byref(cam),
+                                         ctypes.byref(prm), int(width), int(height),
+                                         int(frame_index) & 0xFFFFFFFF, _ptr(out),
+                                         ctypes.byref(rid))
+        check(rc)
+        return int(rid.value)
+
+    submit = cloud_serve_submit
+
+    def try_submit(self, *args):
+        """Like submit, but returns the CLOUD_E_* code instead of raising."""
+        rid = c_uint64(0)
+        stream_id, camera, params, width, height, frame_index, out = args
+        cam, prm = make_camera(camera), make_params(params)
+        rc = self.lib.cloud_serve_submit(self.handle, int(stream_id), ctypes.byref(cam),
+                                         ctypes.byref(prm), int(width), int(height),
+                                         int(frame_index) & 0xFFFFFFFF, _ptr(out),
+                                         ctypes.byref(rid))
+        return rc, int(rid.value)
+
+    def cloud_serve_poll(self, max_items: int = 256):
+        arr = (cloud_completion * max(max_items, 1))()
+        n = c_int32(0)
+        check(self.lib.cloud_serve_poll(self.handle, arr, int(max_items), ctypes.byref(n)))
+        return [{"request_id": int(c.request_id), "stream_id": int(c.stream_id),
+                 "status": int(c.status), "t_submit_ns": int(c.t_submit_ns),
+                 "t_admit_ns": int(c.t_admit_ns), "t_start_ns": int(c.t_start_ns),
+                 "t_done_ns": int(c.t_done_ns)} for c in arr[:n.value]]
+
+    poll = cloud_serve_poll
+
+    def cloud_serve_wait(self, timeout_s: float) -> bool:
+        rc = self.lib.cloud_serve_wait(self.handle, int(timeout_s * 1e9))
+        if rc < 0:
+            check(rc)
+        return rc == 1
+
+    wait = cloud_serve_wait
+
+    def cloud_serve_stats(self) -> dict:
+        s = cloud_serve_stats_t()
+        check(self.lib.cloud_serve_stats(self.handle, ctypes.byref(s)))
+        return {n: int(getattr(s, n)) for n, _ in cloud_serve_stats_t._fields_}
+
+    stats = cloud_serve_stats
+
+    def cloud_serve_close_stream(self, stream_id: int) -> int:
+        return self.lib.cloud_serve_close_stream(self.handle, int(stream_id))
+
+    close_stream = cloud_serve_close_stream
+
+    def cloud_serve_destroy(self):
+        if self.handle is not None and self.handle.value:
+            check(self.lib.cloud_serve_destroy(self.handle))
+        self.handle = None
+
+    destroy = cloud_serve_destroy
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -60,23 +60,41 @@ int check_image(int W, int H, long long views) {
   return CLOUD_OK;
 }
 
-int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
+int volume_layout_bytes(const cloud_volume* v, int layout, size_t* bytes) {
   if (!v) return fail(CLOUD_E_INVALID, "volume is NULL");
-  if (v->layout != 0) return fail(CLOUD_E_INVALID, "volume layout must be 0 (dense)");
+  if (layout < CLOUD_LAYOUT_DENSE || layout > CLOUD_LAYOUT_OCT)
+    return fail(CLOUD_E_INVALID, "unknown volume layout");
   if (dtype_size(v->dtype) == 0) return fail(CLOUD_E_INVALID, "unknown volume dtype");
   if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(CLOUD_E_INVALID, "volume dims must be >= 2");
-  const long long texels = (long long)v->nx * v->ny * v->nz;
-  if (texels > 0x7FFFFFFFLL) return fail(CLOUD_E_INVALID, "volume has more than 2^31-1 texels");
+  // entries (texels, or packed footprints) per plane and in total
+  const long long ex = layout == CLOUD_LAYOUT_DENSE ? v->nx : (long long)v->nx + 1;
+  const long long ey = layout == CLOUD_LAYOUT_DENSE ? v->ny : (long long)v->ny + 1;
+  const long long ez = layout == CLOUD_LAYOUT_OCT ? (long long)v->nz + 1 : v->nz;
+  if (ex * ey >= (1LL << 24)) return fail(CLOUD_E_INVALID, "volume planes must hold < 2^24 texels");
+  if (ex * ey * ez > 0x7FFFFFFFLL) return fail(CLOUD_E_INVALID, "volume has too many texels");
+  const int corners = layout == CLOUD_LAYOUT_DENSE ? 1 : layout == CLOUD_LAYOUT_QUAD ? 4 : 8;
+  *bytes = (size_t)(ex * ey * ez) * corners * dtype_size(v->dtype);
+  return CLOUD_OK;
+}
+
+int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
+  if (!v) return fail(CLOUD_E_INVALID, "volume is NULL");
+  size_t bytes = 0;
+  int rc = volume_layout_bytes(v, v->layout, &bytes);
+  if (rc) return rc;
   for (int k = 0; k < 3; ++k) {
     if (!std::isfinite(v->box_min[k]) || !std::isfinite(v->box_max[k]) ||
         !(v->box_max[k] > v->box_min[k]))
       return fail(CLOUD_E_INVALID, "box_max must exceed box_min on every axis");
   }
-  int rc = check_span(v->base, (size_t)texels * dtype_size(v->dtype), "volume base");
-  if (rc) return rc;
+  if (v->layout != CLOUD_LAYOUT_DENSE && reinterpret_cast<uintptr_t>(v->base) % 16)
+    return fail(CLOUD_E_INVALID, "a packed volume must be 16-byte aligned");
+  if ((rc = check_span(v->base, bytes, "volume base"))) return rc;
   DevVolume d = {};
   d.base = v->base;
   d.nx = v->nx; d.ny = v->ny; d.nz = v->nz;
+  d.row = v->layout == CLOUD_LAYOUT_DENSE ? v->nx : v->nx + 1;
+  d.plane = d.row * (v->layout == CLOUD_LAYOUT_DENSE ? v->ny : v->ny + 1);
   const int n[3] = {v->nx, v->ny, v->nz};
   float* s[3] = {&d.sx, &d.sy, &d.sz};
   float* o[3] = {&d.ox, &d.oy, &d.oz};
@@ -99,6 +117,8 @@ int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
       return fail(CLOUD_E_INVALID, "detail_weight must be in [0, 1)");
     if (!std::isfinite(v->detail_tiling) || !(v->detail_tiling > 0.0f))
       return fail(CLOUD_E_INVALID, "detail_tiling must be > 0");
+    if ((long long)v->dnx * v->dny >= (1LL << 24))
+      return fail(CLOUD_E_INVALID, "detail planes must hold < 2^24 texels");
     rc = check_span(v->detail, (size_t)dt * dtype_size(v->ddtype), "volume detail");
     if (rc) return rc;
     d.detail = v->detail;
@@ -217,10 +237,9 @@ const char* cloud_last_error(void) { return g_last_error.c_str(); }
 
 int cloud_abi_version(void) { return CLOUD_ABI_VERSION; }
 
-int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
+static int render_impl(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
                        const cloud_params* params, uint32_t frame_index, int32_t width,
-                       int32_t height, float* out_rgba, void* hip_stream) {
-  CLOUD_GUARD_BEGIN
+                       int32_t height, float* out_rgba, uint64_t* counts, void* hip_stream) {
   clear_error();
   if (!cameras) return fail(CLOUD_E_INVALID, "cameras is NULL");
   if (n_views < 1) return fail(CLOUD_E_INVALID, "n_views must be >= 1");
@@ -231,10 +250,16 @@ int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras, 
   if ((rc = prepare_volume(volume, &v, &dtype))) return rc;
   DevParams p;
   if ((rc = prepare_params(params, volume, &p))) return rc;
-  if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
-    return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
   const size_t px = (size_t)width * height;
-  if ((rc = check_span(out_rgba, px * 16 * (size_t)n_views, "out_rgba"))) return rc;
+  if (counts) {
+    if (reinterpret_cast<uintptr_t>(counts) % 8)
+      return fail(CLOUD_E_INVALID, "out_count must be 8-byte aligned");
+    if ((rc = check_span(counts, 8, "out_count"))) return rc;
+  } else {
+    if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
+      return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
+    if ((rc = check_span(out_rgba, px * 16 * (size_t)n_views, "out_rgba"))) return rc;
+  }
   DevCameras cams;
   for (int i = 0; i < n_views; ++i) {
     if ((rc = prepare_camera(&cameras[i], width, height, &cams.c[i % kMaxViews]))) return rc;
@@ -242,12 +267,74 @@ int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras, 
     if ((i + 1) % kMaxViews == 0 || last) {
       const int first = i - i % kMaxViews;
       const int count = i - first + 1;
-      hipError_t e = launch_render(v, dtype, p, cams, count, frame_index, width, height,
-                                   out_rgba + (size_t)first * px * 4,
+      hipError_t e = launch_render(v, dtype, volume->layout, p, cams, count, frame_index, width,
+                                   height, counts ? nullptr : out_rgba + (size_t)first * px * 4,
+                                   reinterpret_cast<unsigned long long*>(counts),
                                    static_cast<hipStream_t>(hip_stream));
       if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("render launch: ") + hipGetErrorString(e));
     }
   }
+  return CLOUD_OK;
+}
+
+int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
+                       const cloud_params* params, uint32_t frame_index, int32_t width,
+                       int32_t height, float* out_rgba, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  return render_impl(volume, cameras, n_views, params, frame_index, width, height, out_rgba,
+                     nullptr, hip_stream);
+  CLOUD_GUARD_END
+}
+
+int cloud_count_lookups(const cloud_volume* volume, const cloud_camera* camera,
+                        const cloud_params* params, uint32_t frame_index, int32_t width,
+                        int32_t height, uint64_t* out_count, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  if (!out_count) return fail(CLOUD_E_INVALID, "out_count is NULL");
+  return render_impl(volume, camera, 1, params, frame_index, width, height, nullptr, out_count,
+                     hip_stream);
+  CLOUD_GUARD_END
+}
+
+int cloud_volume_packed_bytes(const cloud_volume* dense, int32_t layout, uint64_t* bytes) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (!bytes) return fail(CLOUD_E_INVALID, "bytes is NULL");
+  size_t b = 0;
+  const int rc = volume_layout_bytes(dense, layout, &b);
+  if (rc) return rc;
+  *bytes = b;
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_volume_pack(const cloud_volume* dense, int32_t layout, void* dst, uint64_t dst_bytes,
+                      cloud_volume* packed, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (!dense) return fail(CLOUD_E_INVALID, "volume is NULL");
+  if (!packed) return fail(CLOUD_E_INVALID, "packed is NULL");
+  if (dense->layout != CLOUD_LAYOUT_DENSE) return fail(CLOUD_E_INVALID, "source volume must be dense");
+  if (layout != CLOUD_LAYOUT_QUAD && layout != CLOUD_LAYOUT_OCT)
+    return fail(CLOUD_E_INVALID, "target layout must be quad (1) or oct (2)");
+  DevVolume v;
+  int dtype, rc;
+  if ((rc = prepare_volume(dense, &v, &dtype))) return rc;
+  size_t need = 0;
+  if ((rc = volume_layout_bytes(dense, layout, &need))) return rc;
+  if (dst_bytes < need) return fail(CLOUD_E_INVALID, "dst is smaller than the packed volume");
+  if (reinterpret_cast<uintptr_t>(dst) % 16) return fail(CLOUD_E_INVALID, "dst must be 16-byte aligned");
+  if ((rc = check_span(dst, need, "dst"))) return rc;
+  const char* d0 = static_cast<const char*>(dst);
+  const char* s0 = static_cast<const char*>(dense->base);
+  const size_t sbytes = (size_t)dense->nx * dense->ny * dense->nz * dtype_size(dtype);
+  if (d0 < s0 + sbytes && s0 < d0 + need) return fail(CLOUD_E_INVALID, "dst overlaps the volume");
+  hipError_t e = launch_pack(dense->base, (int)dtype_size(dtype), dense->nx, dense->ny, dense->nz,
+                             layout, dst, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("pack launch: ") + hipGetErrorString(e));
+  *packed = *dense;
+  packed->base = dst;
+  packed->layout = layout;
   return CLOUD_OK;
   CLOUD_GUARD_END
 }
@@ -279,7 +366,8 @@ int cloud_march_rays(const cloud_volume* volume, const float* origins, const flo
   if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
     return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
   if ((rc = check_span(out_rgba, (size_t)n * 16, "out_rgba"))) return rc;
-  hipError_t e = launch_rays(v, dtype, p, frame_index, origins, dirs, pixel_xy, n, out_rgba,
+  hipError_t e = launch_rays(v, dtype, volume->layout, p, frame_index, origins, dirs, pixel_xy, n,
+                             out_rgba,
                              static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("march launch: ") + hipGetErrorString(e));
   return CLOUD_OK;
@@ -312,6 +400,20 @@ int cloud_taa_resolve(const float* current, const float* history, float* out, in
                             static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
   return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_tune(const char* key, int32_t value) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (!key) return fail(CLOUD_E_INVALID, "key is NULL");
+  const std::string k(key);
+  if (k == "supertile") {
+    if (value < 0 || value > 64) return fail(CLOUD_E_INVALID, "supertile must be in [0, 64]");
+    tuning().supertile = value;
+    return CLOUD_OK;
+  }
+  return fail(CLOUD_E_INVALID, "unknown tuning key " + k);
   CLOUD_GUARD_END
 }
 

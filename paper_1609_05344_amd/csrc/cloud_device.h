@@ -14,6 +14,15 @@ namespace cloud {
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 
+#ifndef CLOUD_LIGHT_UNROLL
+#define CLOUD_LIGHT_UNROLL 6
+#endif
+// Light-march lookups issued back to back (independent loads in flight).
+constexpr int kLightUnroll = CLOUD_LIGHT_UNROLL;
+#ifndef CLOUD_PREFETCH
+#define CLOUD_PREFETCH 0
+#endif
+
 // PCG-RXS-M-XS 32-bit hash (Jarzynski and Olano, JCGT 2020).
 __device__ __forceinline__ uint32_t pcg(uint32_t v) {
   uint32_t s = v * 747796405u + 2891336453u;
@@ -29,6 +38,12 @@ __device__ __forceinline__ float jitter_offset(uint32_t px, uint32_t py, uint32_
   return (float)(h >> 8) * 5.9604644775390625e-8f;
 }
 
+// ---------------------------------------------------------------------------
+// Texel decoding
+// ---------------------------------------------------------------------------
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
 template <int DT>
 __device__ __forceinline__ float texel(const void* __restrict__ base, int idx) {
   if constexpr (DT == DT_F32) {
@@ -40,32 +55,130 @@ __device__ __forceinline__ float texel(const void* __restrict__ base, int idx) {
   }
 }
 
+// Two 16-bit texels packed in a word (low half first) -> two floats.
+template <int DT>
+__device__ __forceinline__ void unpack2(uint32_t u, float& lo, float& hi) {
+  if constexpr (DT == DT_F16) {
+    const half2_t h = __builtin_bit_cast(half2_t, u);
+    lo = (float)h.x;
+    hi = (float)h.y;
+  } else {
+    lo = __uint_as_float(u << 16);
+    hi = __uint_as_float(u & 0xFFFF0000u);
+  }
+}
+
 __device__ __forceinline__ float lerp(float a, float b, float w) { return fmaf(w, b - a, a); }
 
-// Trilinear lookup with clamp-to-edge at continuous texel coordinates
-// (x, then y, then z). Coordinates are first bounded to [-1, n], which leaves
-// the clamped result unchanged and keeps every index inside the volume for
-// any input, NaN included.
-template <int DT>
-__device__ __forceinline__ float trilerp_clamp(const void* __restrict__ base, int nx, int ny,
-                                               int nz, float fx, float fy, float fz) {
-  fx = fminf(fmaxf(fx, -1.0f), (float)nx);
-  fy = fminf(fmaxf(fy, -1.0f), (float)ny);
-  fz = fminf(fmaxf(fz, -1.0f), (float)nz);
-  const float x0f = floorf(fx), y0f = floorf(fy), z0f = floorf(fz);
-  const float wx = fx - x0f, wy = fy - y0f, wz = fz - z0f;
-  const int x0 = (int)x0f, y0 = (int)y0f, z0 = (int)z0f;
-  const int xa = min(max(x0, 0), nx - 1), xb = min(max(x0 + 1, 0), nx - 1);
-  const int ya = min(max(y0, 0), ny - 1), yb = min(max(y0 + 1, 0), ny - 1);
-  const int za = min(max(z0, 0), nz - 1), zb = min(max(z0 + 1, 0), nz - 1);
-  const int r00 = (za * ny + ya) * nx, r10 = (za * ny + yb) * nx;
-  const int r01 = (zb * ny + ya) * nx, r11 = (zb * ny + yb) * nx;
-  const float c00 = lerp(texel<DT>(base, r00 + xa), texel<DT>(base, r00 + xb), wx);
-  const float c10 = lerp(texel<DT>(base, r10 + xa), texel<DT>(base, r10 + xb), wx);
-  const float c01 = lerp(texel<DT>(base, r01 + xa), texel<DT>(base, r01 + xb), wx);
-  const float c11 = lerp(texel<DT>(base, r11 + xa), texel<DT>(base, r11 + xb), wx);
-  return lerp(lerp(c00, c10, wy), lerp(c01, c11, wy), wz);
+// Continuous texel coordinate bounded to [-1, n]: leaves every clamped lookup
+// unchanged and keeps every index inside the volume for any input (NaN too).
+__device__ __forceinline__ void split_coord(float f, int n, float& w, int& k) {
+  f = fminf(fmaxf(f, -1.0f), (float)n);
+  const float fl = floorf(f);
+  w = f - fl;
+  k = (int)fl;   // in [-1, n]
 }
+
+// ---------------------------------------------------------------------------
+// Base-volume trilinear lookup with clamp-to-edge, x then y then z
+// ---------------------------------------------------------------------------
+
+template <int DT, int LAYOUT>
+struct BaseSampler;
+
+// Dense [nz][ny][nx]: eight texel fetches per lookup.
+template <int DT>
+struct BaseSampler<DT, LAYOUT_DENSE> {
+  __device__ static __forceinline__ float fetch(const DevVolume& v, float fx, float fy, float fz) {
+    float wx, wy, wz;
+    int kx, ky, kz;
+    split_coord(fx, v.nx, wx, kx);
+    split_coord(fy, v.ny, wy, ky);
+    split_coord(fz, v.nz, wz, kz);
+    const int xa = min(max(kx, 0), v.nx - 1), xb = min(max(kx + 1, 0), v.nx - 1);
+    const int ya = min(max(ky, 0), v.ny - 1), yb = min(max(ky + 1, 0), v.ny - 1);
+    const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
+    // indices stay below 2^31 and plane < 2^24 (checked on the host), so the
+    // 24-bit multiplies are exact
+    const int ra = __umul24(ya, v.row), rb = __umul24(yb, v.row);
+    const int pa = __umul24(za, v.plane), pb = __umul24(zb, v.plane);
+    const float c00 = lerp(texel<DT>(v.base, pa + ra + xa), texel<DT>(v.base, pa + ra + xb), wx);
+    const float c10 = lerp(texel<DT>(v.base, pa + rb + xa), texel<DT>(v.base, pa + rb + xb), wx);
+    const float c01 = lerp(texel<DT>(v.base, pb + ra + xa), texel<DT>(v.base, pb + ra + xb), wx);
+    const float c11 = lerp(texel<DT>(v.base, pb + rb + xa), texel<DT>(v.base, pb + rb + xb), wx);
+    return lerp(lerp(c00, c10, wy), lerp(c01, c11, wy), wz);
+  }
+};
+
+// Entry of corner k (in [-1, n-1] per axis) of a packed volume.
+__device__ __forceinline__ int packed_xy(const DevVolume& v, int kx, int ky) {
+  return __umul24(min(ky, v.ny - 1) + 1, v.row) + min(kx, v.nx - 1) + 1;
+}
+
+// Quad layout [nz][ny+1][nx+1] x 4: entry (z, y, x) holds the texels at
+// (x, y), (x+1, y), (x, y+1), (x+1, y+1) of plane z (edge-clamped), so a
+// lookup is two aligned fetches, one per z plane.
+template <int DT>
+struct BaseSampler<DT, LAYOUT_QUAD> {
+  __device__ static __forceinline__ float fetch(const DevVolume& v, float fx, float fy, float fz) {
+    float wx, wy, wz;
+    int kx, ky, kz;
+    split_coord(fx, v.nx, wx, kx);
+    split_coord(fy, v.ny, wy, ky);
+    split_coord(fz, v.nz, wz, kz);
+    const int e = packed_xy(v, kx, ky);
+    const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
+    const int ea = __umul24(za, v.plane) + e, eb = __umul24(zb, v.plane) + e;
+    float a0, a1, a2, a3, b0, b1, b2, b3;
+    if constexpr (DT == DT_F32) {
+      const float4* q = static_cast<const float4*>(v.base);
+      const float4 A = q[ea], B = q[eb];
+      a0 = A.x; a1 = A.y; a2 = A.z; a3 = A.w;
+      b0 = B.x; b1 = B.y; b2 = B.z; b3 = B.w;
+    } else {
+      const uint2* q = static_cast<const uint2*>(v.base);
+      const uint2 A = q[ea], B = q[eb];
+      unpack2<DT>(A.x, a0, a1);
+      unpack2<DT>(A.y, a2, a3);
+      unpack2<DT>(B.x, b0, b1);
+      unpack2<DT>(B.y, b2, b3);
+    }
+    const float c0 = lerp(lerp(a0, a1, wx), lerp(a2, a3, wx), wy);
+    const float c1 = lerp(lerp(b0, b1, wx), lerp(b2, b3, wx), wy);
+    return lerp(c0, c1, wz);
+  }
+};
+
+// Oct layout [nz+1][ny+1][nx+1] x 8: entry (z, y, x) holds the whole 2x2x2
+// footprint (the quad of plane z, then the quad of plane z+1, edge-clamped),
+// so a lookup is one aligned fetch (two for float32).
+template <int DT>
+struct BaseSampler<DT, LAYOUT_OCT> {
+  __device__ static __forceinline__ float fetch(const DevVolume& v, float fx, float fy, float fz) {
+    float wx, wy, wz;
+    int kx, ky, kz;
+    split_coord(fx, v.nx, wx, kx);
+    split_coord(fy, v.ny, wy, ky);
+    split_coord(fz, v.nz, wz, kz);
+    const int e = __umul24(min(kz, v.nz - 1) + 1, v.plane) + packed_xy(v, kx, ky);
+    float a0, a1, a2, a3, b0, b1, b2, b3;
+    if constexpr (DT == DT_F32) {
+      const float4* q = static_cast<const float4*>(v.base) + 2 * (size_t)e;
+      const float4 A = q[0], B = q[1];
+      a0 = A.x; a1 = A.y; a2 = A.z; a3 = A.w;
+      b0 = B.x; b1 = B.y; b2 = B.z; b3 = B.w;
+    } else {
+      const uint4 Q = static_cast<const uint4*>(v.base)[e];
+      unpack2<DT>(Q.x, a0, a1);
+      unpack2<DT>(Q.y, a2, a3);
+      unpack2<DT>(Q.z, b0, b1);
+      unpack2<DT>(Q.w, b2, b3);
+    }
+    const float c0 = lerp(lerp(a0, a1, wx), lerp(a2, a3, wx), wy);
+    const float c1 = lerp(lerp(b0, b1, wx), lerp(b2, b3, wx), wy);
+    return lerp(c0, c1, wz);
+  }
+};
 
 // Index k of a periodic axis of n texels, wrapped into [0, n).
 __device__ __forceinline__ int wrap_index(int k, int n) {
@@ -73,7 +186,7 @@ __device__ __forceinline__ int wrap_index(int k, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Trilinear lookup with repeat addressing (the tiled detail volume).
+// Trilinear lookup with repeat addressing (the tiled detail volume, dense).
 template <int DT>
 __device__ __forceinline__ float trilerp_repeat(const void* __restrict__ base, int nx, int ny,
                                                 int nz, float fx, float fy, float fz) {
@@ -100,10 +213,10 @@ __device__ __forceinline__ float trilerp_repeat(const void* __restrict__ base, i
 // Density at world point p (Section 1). With a detail volume the base shape
 // is eroded: clamp((b - w d) / (1 - w d), 0, 1); where b <= 0 the result is 0
 // whatever d is, so the detail lookup is skipped there.
-template <int DT, bool DETAIL>
+template <int DT, int LAYOUT, bool DETAIL>
 __device__ __forceinline__ float density(const DevVolume& v, float px, float py, float pz) {
-  const float b = trilerp_clamp<DT>(v.base, v.nx, v.ny, v.nz, fmaf(px, v.sx, v.ox),
-                                    fmaf(py, v.sy, v.oy), fmaf(pz, v.sz, v.oz));
+  const float b = BaseSampler<DT, LAYOUT>::fetch(v, fmaf(px, v.sx, v.ox), fmaf(py, v.sy, v.oy),
+                                                 fmaf(pz, v.sz, v.oz));
   if constexpr (!DETAIL) {
     return b;
   } else {
@@ -117,7 +230,7 @@ __device__ __forceinline__ float density(const DevVolume& v, float px, float py,
 
 // Transmittance towards the sun from p (Section 1): L midpoint samples of
 // equal steps up to the box exit along s, Beer-Lambert over their sum.
-template <int DT, bool DETAIL>
+template <int DT, int LAYOUT, bool DETAIL>
 __device__ __forceinline__ float light_transmittance(const DevVolume& v, const DevParams& P,
                                                      float px, float py, float pz) {
   float tx = 3.402823466e38f;
@@ -127,24 +240,26 @@ __device__ __forceinline__ float light_transmittance(const DevVolume& v, const D
   const float dl = tx * P.inv_light_steps;
   const float stx = dl * P.s[0], sty = dl * P.s[1], stz = dl * P.s[2];
   float acc = 0.0f;
+#pragma unroll kLightUnroll
   for (int k = 0; k < P.light_steps; ++k) {
     const float h = (float)k + 0.5f;
-    acc += density<DT, DETAIL>(v, fmaf(h, stx, px), fmaf(h, sty, py), fmaf(h, stz, pz));
+    acc += density<DT, LAYOUT, DETAIL>(v, fmaf(h, stx, px), fmaf(h, sty, py), fmaf(h, stz, pz));
   }
   return exp2f(-P.alpha_log2e * dl * acc);
 }
 
 struct RayResult {
   float r, g, b, a;
+  uint32_t lookups;   // density lookups performed (counted only on request)
 };
 
 // One primary ray through the volume (Sections 1, 3.1, 3.2). (o, d): origin
 // and unit direction; j: start offset in [0, 1).
-template <int DT, bool DETAIL, int INTEG>
+template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
 __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& P, float ox,
                                            float oy, float oz, float dx, float dy, float dz,
                                            float j) {
-  RayResult res = {0.0f, 0.0f, 0.0f, 0.0f};
+  RayResult res = {0.0f, 0.0f, 0.0f, 0.0f, 0u};
   // slab test; an axis with d_k == 0 passes iff the origin lies in the slab
   float tn = 0.0f, tf = 3.402823466e38f;
   bool hit = true;
@@ -168,30 +283,55 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
   const float phase = P.hg_k / (q * sqrtf(q));
   const float sr = P.sun[0] * phase, sg = P.sun[1] * phase, sb = P.sun[2] * phase;
   const float kx = P.alpha_log2e * D;   // exp2 scale of rho for one step
+  const float xD = P.alpha * D;         // optical depth per unit density for one step
 
   float T = 1.0f, Sr = 0.0f, Sg = 0.0f, Sb = 0.0f;
+  uint32_t n = 0;
+#if CLOUD_PREFETCH
+  // The next sample's density is fetched before this sample's light march,
+  // so its latency overlaps the light lookups (results are unchanged; a
+  // fetch past an early exit is simply not used).
+  float rho_next;
+  {
+    const float t0 = fmaf(j, D, tn);
+    rho_next = density<DT, LAYOUT, DETAIL>(v, fmaf(t0, dx, ox), fmaf(t0, dy, oy), fmaf(t0, dz, oz));
+  }
+#endif
   for (int i = 0; i < P.steps; ++i) {
     const float t = fmaf((float)i + j, D, tn);
     const float px = fmaf(t, dx, ox), py = fmaf(t, dy, oy), pz = fmaf(t, dz, oz);
-    const float rho = density<DT, DETAIL>(v, px, py, pz);
+#if CLOUD_PREFETCH
+    const float rho = rho_next;
+    if (i + 1 < P.steps) {
+      const float t1 = fmaf((float)(i + 1) + j, D, tn);
+      rho_next = density<DT, LAYOUT, DETAIL>(v, fmaf(t1, dx, ox), fmaf(t1, dy, oy), fmaf(t1, dz, oz));
+    }
+#else
+    const float rho = density<DT, LAYOUT, DETAIL>(v, px, py, pz);
+#endif
+    if constexpr (COUNT) n += 1;
     if (rho > 0.0f) {
-      const float TL = P.light_steps > 0 ? light_transmittance<DT, DETAIL>(v, P, px, py, pz) : 1.0f;
+      float TL = 1.0f;
+      if (P.light_steps > 0) {
+        TL = light_transmittance<DT, LAYOUT, DETAIL>(v, P, px, py, pz);
+        if constexpr (COUNT) n += (uint32_t)P.light_steps;
+      }
       const float lr = fmaf(sr, TL, P.amb[0]), lg = fmaf(sg, TL, P.amb[1]),
                   lb = fmaf(sb, TL, P.amb[2]);
       const float e = exp2f(-rho * kx);
-      if constexpr (INTEG == 1) {
-        const float w = T * (1.0f - e);
-        Sr = fmaf(w, lr, Sr);
-        Sg = fmaf(w, lg, Sg);
-        Sb = fmaf(w, lb, Sb);
+      float w;
+      if (P.integration) {
+        // Section 3.1: T0 L_in (1 - e^{-rho alpha D}), then the T update
+        w = T * (1.0f - e);
         T *= e;
       } else {
+        // the basic rule: update T first, then S += T rho alpha D L_in
         T *= e;
-        const float w = T * (rho * P.alpha * D);
-        Sr = fmaf(w, lr, Sr);
-        Sg = fmaf(w, lg, Sg);
-        Sb = fmaf(w, lb, Sb);
+        w = T * (rho * xD);
       }
+      Sr = fmaf(w, lr, Sr);
+      Sg = fmaf(w, lg, Sg);
+      Sb = fmaf(w, lb, Sb);
       if (T < P.t_eps) break;
     }
   }
@@ -199,6 +339,7 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
   res.g = Sg;
   res.b = Sb;
   res.a = 1.0f - T;
+  res.lookups = n;
   return res;
 }
 
@@ -223,6 +364,38 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int q = nb >> 3, r = nb & 7;
   const int x = b & 7, k = b >> 3;
   return x * q + min(x, r) + k;
+}
+
+// Ordered tile index k of one view -> tile (tx, ty). Tiles are walked in
+// super-tiles of S x S tiles (super-tile rows top to bottom, super-tiles left
+// to right, tiles row-major inside; edge super-tiles are narrower/shorter), so
+// that a contiguous run of k -- what one XCD works on at a time -- covers a
+// compact patch of the image, whose rays read a compact part of the volume.
+// S == 0 walks the tiles row-major. The map is a bijection on [0, tx * ty).
+__device__ __forceinline__ void supertile(int k, int tiles_x, int tiles_y, int S, int& tx,
+                                          int& ty) {
+  if (S <= 0) {
+    ty = k / tiles_x;
+    tx = k - ty * tiles_x;
+    return;
+  }
+  const int band = S * tiles_x;                 // tiles in a full super-tile row
+  const int R = min(k / band, (tiles_y - 1) / S);
+  const int h = min(S, tiles_y - R * S);        // height of this super-tile row
+  const int o = k - R * band;
+  const int C = o / (S * h);
+  const int w = min(S, tiles_x - C * S);
+  const int l = o - C * S * h;
+  const int lr = l / w;
+  ty = R * S + lr;
+  tx = C * S + (l - lr * w);
+}
+
+// Sum of a 32-bit value over the wavefront (all 64 lanes must be active).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
 }
 
 }  // namespace cloud

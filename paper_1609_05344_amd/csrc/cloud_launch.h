@@ -7,14 +7,27 @@
 
 namespace cloud {
 
-// Render n_views (<= kMaxViews) cameras into out [n_views][H][W][4].
-hipError_t launch_render(const DevVolume& v, int dtype, const DevParams& p, const DevCameras& c,
-                         int n_views, uint32_t frame, int W, int H, float* out, hipStream_t s);
+// Launch-shape knobs (process-wide; set through cloud_tune).
+struct Tuning {
+  int supertile = 4;   // render tile walk: S x S super-tiles (0 = row-major)
+};
+Tuning& tuning();
+
+// Render n_views (<= kMaxViews) cameras into out [n_views][H][W][4]; with
+// counts != nullptr, add the density lookups to *counts instead (no image).
+hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevParams& p,
+                         const DevCameras& c, int n_views, uint32_t frame, int W, int H,
+                         float* out, unsigned long long* counts, hipStream_t s);
 
 // March n explicit rays into out [n][4].
-hipError_t launch_rays(const DevVolume& v, int dtype, const DevParams& p, uint32_t frame,
-                       const float* o, const float* d, const uint32_t* pxy, long long n,
-                       float* out, hipStream_t s);
+hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParams& p,
+                       uint32_t frame, const float* o, const float* d, const uint32_t* pxy,
+                       long long n, float* out, hipStream_t s);
+
+// Pack a dense [nz][ny][nx] volume of 2- or 4-byte texels into a quad or oct
+// layout at dst.
+hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,
+                       void* dst, hipStream_t s);
 
 // Jitter offsets (as integers j * 2^24) of n pixels.
 hipError_t launch_jitter(const uint32_t* pxy, long long n, uint32_t frame, uint32_t seed,

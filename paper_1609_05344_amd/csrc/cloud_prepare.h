@@ -16,6 +16,8 @@ void clear_error();
 
 // Each returns CLOUD_OK or CLOUD_E_INVALID (with the message set).
 int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype);
+// Device bytes of v's base volume stored in `layout` (checks the dims).
+int volume_layout_bytes(const cloud_volume* v, int layout, size_t* bytes);
 int prepare_params(const cloud_params* p, const cloud_volume* v, DevParams* out);
 int prepare_camera(const cloud_camera* c, int W, int H, DevCamera* out);
 int check_image(int W, int H, long long views);

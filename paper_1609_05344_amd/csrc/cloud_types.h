@@ -12,9 +12,15 @@ namespace cloud {
 
 constexpr int kMaxViews = 16;   // cameras carried by value in one launch
 
+// Base-volume layouts. All hold the same texel values; the packed ones
+// replicate each lookup's footprint so that it is one aligned fetch.
+enum { LAYOUT_DENSE = 0, LAYOUT_QUAD = 1, LAYOUT_OCT = 2 };
+
 struct DevVolume {
   const void* base;
   int nx, ny, nz;
+  int plane;            // dense: nx * ny; packed: (nx + 1) * (ny + 1) entries
+  int row;              // dense: nx; packed: nx + 1 entries
   // continuous texel coordinate along each axis: f = p * s + o, texel k's
   // centre at f = k (texel centres at box_min + (k + 0.5) * extent / n)
   float sx, sy, sz, ox, oy, oz;

@@ -1,4 +1,5 @@
-// Render, explicit-ray and temporal-resolve kernels, and their launchers.
+// Render, explicit-ray, lookup-count, volume-pack and temporal-resolve
+// kernels, and their launchers.
 #include <hip/hip_runtime.h>
 
 #include "cloud_device.h"
@@ -6,36 +7,53 @@
 
 namespace cloud {
 
+Tuning& tuning() {
+  static Tuning t;
+  return t;
+}
+
 // ---------------------------------------------------------------------------
-// cloud_render / cloud_render_views: one thread per pixel. A 256-thread
-// workgroup covers a 16x16 pixel tile as four 8x8 wave tiles, so the 64 rays
-// of a wavefront are a compact bundle that samples neighbouring texels.
+// cloud_render / cloud_render_views / cloud_count_lookups: one thread per
+// pixel. A 256-thread workgroup covers a 16x16 pixel tile as four 8x8 wave
+// tiles, so the 64 rays of a wavefront are a compact bundle that samples
+// neighbouring texels. COUNT adds up the density lookups instead of storing
+// the image.
 // ---------------------------------------------------------------------------
 
-template <int DT, bool DETAIL, int INTEG>
+template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
 __global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams prm,
                                                      DevCameras cams, uint32_t frame, int W,
-                                                     int H, int tiles_x, int tiles_per_view,
-                                                     float4* __restrict__ out) {
+                                                     int H, int tiles_x, int tiles_y, int S,
+                                                     float4* __restrict__ out,
+                                                     unsigned long long* __restrict__ counts) {
+  const int tiles_per_view = tiles_x * tiles_y;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int view = tile / tiles_per_view;
-  const int t = tile - view * tiles_per_view;
-  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  int tx, ty;
+  supertile(tile - view * tiles_per_view, tiles_x, tiles_y, S, tx, ty);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int px = tx * 16 + (wave & 1) * 8 + (lane & 7);
   const int py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
-  if (px >= W || py >= H) return;
+  const bool inside = px < W && py < H;
+  if (!COUNT && !inside) return;
 
-  const DevCamera& c = cams.c[view];
-  float dx, dy, dz;
-  camera_dir(c, px, py, W, H, dx, dy, dz);
-  const float j = prm.jitter ? jitter_offset((uint32_t)px, (uint32_t)py, frame, prm.seed) : 0.5f;
-  const RayResult r = march<DT, DETAIL, INTEG>(vol, prm, c.pos[0], c.pos[1], c.pos[2], dx, dy,
-                                               dz, j);
-  out[((size_t)view * H + py) * W + px] = make_float4(r.r, r.g, r.b, r.a);
+  RayResult r = {0.0f, 0.0f, 0.0f, 0.0f, 0u};
+  if (inside) {
+    const DevCamera& c = cams.c[view];
+    float dx, dy, dz;
+    camera_dir(c, px, py, W, H, dx, dy, dz);
+    const float j = prm.jitter ? jitter_offset((uint32_t)px, (uint32_t)py, frame, prm.seed) : 0.5f;
+    r = march<DT, LAYOUT, DETAIL, COUNT>(vol, prm, c.pos[0], c.pos[1], c.pos[2], dx, dy, dz, j);
+  }
+  if constexpr (COUNT) {
+    const uint32_t s = wave_sum(r.lookups);
+    if (lane == 0) atomicAdd(counts, (unsigned long long)s);
+  } else {
+    out[((size_t)view * H + py) * W + px] = make_float4(r.r, r.g, r.b, r.a);
+  }
 }
 
-template <int DT, bool DETAIL, int INTEG>
+template <int DT, int LAYOUT, bool DETAIL>
 __global__ __launch_bounds__(256) void rays_kernel(DevVolume vol, DevParams prm, uint32_t frame,
                                                    const float* __restrict__ origins,
                                                    const float* __restrict__ dirs,
@@ -51,8 +69,40 @@ __global__ __launch_bounds__(256) void rays_kernel(DevVolume vol, DevParams prm,
   dz *= inv;
   float j = 0.5f;
   if (prm.jitter && pixel_xy) j = jitter_offset(pixel_xy[2 * i], pixel_xy[2 * i + 1], frame, prm.seed);
-  const RayResult r = march<DT, DETAIL, INTEG>(vol, prm, ox, oy, oz, dx, dy, dz, j);
+  const RayResult r = march<DT, LAYOUT, DETAIL, false>(vol, prm, ox, oy, oz, dx, dy, dz, j);
   out[i] = make_float4(r.r, r.g, r.b, r.a);
+}
+
+// ---------------------------------------------------------------------------
+// Volume packing: entry (z', y', x') of a packed layout holds the texels of
+// the corner k = (x'-1, y'-1, z'-1) and its +1 neighbours, edge-clamped
+// (quad: x and y only, plane z = z'). Storage values are copied bit for bit.
+// ---------------------------------------------------------------------------
+
+template <typename E, int CORNERS>
+__global__ __launch_bounds__(256) void pack_kernel(const E* __restrict__ src, int nx, int ny,
+                                                   int nz, int ez, E* __restrict__ dst) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ex = nx + 1, ey = ny + 1;
+  if (e >= ex * ey * ez) return;
+  const int x = (int)(e % ex) - 1;
+  const int y = (int)((e / ex) % ey) - 1;
+  const int z = (int)(e / (ex * ey)) - (CORNERS == 8 ? 1 : 0);
+  const int xa = min(max(x, 0), nx - 1), xb = min(max(x + 1, 0), nx - 1);
+  const int ya = min(max(y, 0), ny - 1), yb = min(max(y + 1, 0), ny - 1);
+  const int za = min(max(z, 0), nz - 1), zb = min(max(z + 1, 0), nz - 1);
+  const size_t pa = (size_t)za * ny * nx, pb = (size_t)zb * ny * nx;
+  E* o = dst + (size_t)e * CORNERS;
+  o[0] = src[pa + (size_t)ya * nx + xa];
+  o[1] = src[pa + (size_t)ya * nx + xb];
+  o[2] = src[pa + (size_t)yb * nx + xa];
+  o[3] = src[pa + (size_t)yb * nx + xb];
+  if constexpr (CORNERS == 8) {
+    o[4] = src[pb + (size_t)ya * nx + xa];
+    o[5] = src[pb + (size_t)ya * nx + xb];
+    o[6] = src[pb + (size_t)yb * nx + xa];
+    o[7] = src[pb + (size_t)yb * nx + xb];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -112,60 +162,109 @@ __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ sr
 }
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Launchers: runtime (dtype, layout, detail, count) -> template instance
 // ---------------------------------------------------------------------------
 
-template <int DT, bool DETAIL, int INTEG>
-static hipError_t launch_render_t(const DevVolume& v, const DevParams& p, const DevCameras& c,
-                                  int n_views, uint32_t frame, int W, int H, float* out,
-                                  hipStream_t s) {
-  const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
-  const int tiles_per_view = tiles_x * tiles_y;
-  const int blocks = tiles_per_view * n_views;
-  hipLaunchKernelGGL((render_kernel<DT, DETAIL, INTEG>), dim3(blocks), dim3(256), 0, s, v, p, c,
-                     frame, W, H, tiles_x, tiles_per_view, reinterpret_cast<float4*>(out));
+template <typename F, int DT, int LAYOUT>
+static hipError_t dispatch_dc(bool detail, bool count, F& f) {
+  if (detail) return count ? f.template run<DT, LAYOUT, true, true>()
+                           : f.template run<DT, LAYOUT, true, false>();
+  return count ? f.template run<DT, LAYOUT, false, true>() : f.template run<DT, LAYOUT, false, false>();
+}
+
+template <typename F, int DT>
+static hipError_t dispatch_l(int layout, bool detail, bool count, F& f) {
+  switch (layout) {
+    case LAYOUT_QUAD: return dispatch_dc<F, DT, LAYOUT_QUAD>(detail, count, f);
+    case LAYOUT_OCT: return dispatch_dc<F, DT, LAYOUT_OCT>(detail, count, f);
+    default: return dispatch_dc<F, DT, LAYOUT_DENSE>(detail, count, f);
+  }
+}
+
+template <typename F>
+static hipError_t dispatch(int dtype, int layout, bool detail, bool count, F& f) {
+  switch (dtype) {
+    case DT_F16: return dispatch_l<F, DT_F16>(layout, detail, count, f);
+    case DT_BF16: return dispatch_l<F, DT_BF16>(layout, detail, count, f);
+    default: return dispatch_l<F, DT_F32>(layout, detail, count, f);
+  }
+}
+
+struct RenderLaunch {
+  const DevVolume& v;
+  const DevParams& p;
+  const DevCameras& c;
+  int n_views;
+  uint32_t frame;
+  int W, H;
+  float* out;
+  unsigned long long* counts;
+  hipStream_t s;
+  template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+  hipError_t run() {
+    const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+    const int tiles_per_view = tiles_x * tiles_y;
+    const int blocks = tiles_per_view * n_views;
+    hipLaunchKernelGGL((render_kernel<DT, LAYOUT, DETAIL, COUNT>), dim3(blocks), dim3(256), 0, s,
+                       v, p, c, frame, W, H, tiles_x, tiles_y, tuning().supertile,
+                       reinterpret_cast<float4*>(out), counts);
+    return hipGetLastError();
+  }
+};
+
+struct RaysLaunch {
+  const DevVolume& v;
+  const DevParams& p;
+  uint32_t frame;
+  const float *o, *d;
+  const uint32_t* pxy;
+  long long n;
+  float* out;
+  hipStream_t s;
+  template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+  hipError_t run() {
+    const long long blocks = (n + 255) / 256;
+    hipLaunchKernelGGL((rays_kernel<DT, LAYOUT, DETAIL>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       v, p, frame, o, d, pxy, n, reinterpret_cast<float4*>(out));
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevParams& p,
+                         const DevCameras& c, int n_views, uint32_t frame, int W, int H,
+                         float* out, unsigned long long* counts, hipStream_t s) {
+  RenderLaunch f{v, p, c, n_views, frame, W, H, out, counts, s};
+  return dispatch(dtype, layout, v.detail != nullptr, counts != nullptr, f);
+}
+
+hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParams& p,
+                       uint32_t frame, const float* o, const float* d, const uint32_t* pxy,
+                       long long n, float* out, hipStream_t s) {
+  RaysLaunch f{v, p, frame, o, d, pxy, n, out, s};
+  return dispatch(dtype, layout, v.detail != nullptr, false, f);
+}
+
+hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,
+                       void* dst, hipStream_t s) {
+  const int ez = layout == LAYOUT_OCT ? nz + 1 : nz;
+  const long long entries = (long long)(nx + 1) * (ny + 1) * ez;
+  const unsigned blocks = (unsigned)((entries + 255) / 256);
+  if (elem_bytes == 4) {
+    if (layout == LAYOUT_OCT)
+      hipLaunchKernelGGL((pack_kernel<uint32_t, 8>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, static_cast<uint32_t*>(dst));
+    else
+      hipLaunchKernelGGL((pack_kernel<uint32_t, 4>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, static_cast<uint32_t*>(dst));
+  } else {
+    if (layout == LAYOUT_OCT)
+      hipLaunchKernelGGL((pack_kernel<uint16_t, 8>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, static_cast<uint16_t*>(dst));
+    else
+      hipLaunchKernelGGL((pack_kernel<uint16_t, 4>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, static_cast<uint16_t*>(dst));
+  }
   return hipGetLastError();
-}
-
-template <int DT, bool DETAIL, int INTEG>
-static hipError_t launch_rays_t(const DevVolume& v, const DevParams& p, uint32_t frame,
-                                const float* o, const float* d, const uint32_t* pxy, long long n,
-                                float* out, hipStream_t s) {
-  const long long blocks = (n + 255) / 256;
-  hipLaunchKernelGGL((rays_kernel<DT, DETAIL, INTEG>), dim3((unsigned)blocks), dim3(256), 0, s,
-                     v, p, frame, o, d, pxy, n, reinterpret_cast<float4*>(out));
-  return hipGetLastError();
-}
-
-#define CLOUD_DISPATCH(FN, dt, detail, integ, ...)                                 \
-  do {                                                                             \
-    if (dt == DT_F32) {                                                            \
-      if (detail) return integ ? FN<DT_F32, true, 1>(__VA_ARGS__)                  \
-                               : FN<DT_F32, true, 0>(__VA_ARGS__);                 \
-      return integ ? FN<DT_F32, false, 1>(__VA_ARGS__) : FN<DT_F32, false, 0>(__VA_ARGS__); \
-    } else if (dt == DT_F16) {                                                     \
-      if (detail) return integ ? FN<DT_F16, true, 1>(__VA_ARGS__)                  \
-                               : FN<DT_F16, true, 0>(__VA_ARGS__);                 \
-      return integ ? FN<DT_F16, false, 1>(__VA_ARGS__) : FN<DT_F16, false, 0>(__VA_ARGS__); \
-    } else {                                                                       \
-      if (detail) return integ ? FN<DT_BF16, true, 1>(__VA_ARGS__)                 \
-                               : FN<DT_BF16, true, 0>(__VA_ARGS__);                \
-      return integ ? FN<DT_BF16, false, 1>(__VA_ARGS__) : FN<DT_BF16, false, 0>(__VA_ARGS__); \
-    }                                                                              \
-  } while (0)
-
-hipError_t launch_render(const DevVolume& v, int dtype, const DevParams& p, const DevCameras& c,
-                         int n_views, uint32_t frame, int W, int H, float* out, hipStream_t s) {
-  const bool detail = v.detail != nullptr;
-  CLOUD_DISPATCH(launch_render_t, dtype, detail, p.integration, v, p, c, n_views, frame, W, H,
-                 out, s);
-}
-
-hipError_t launch_rays(const DevVolume& v, int dtype, const DevParams& p, uint32_t frame,
-                       const float* o, const float* d, const uint32_t* pxy, long long n,
-                       float* out, hipStream_t s) {
-  const bool detail = v.detail != nullptr;
-  CLOUD_DISPATCH(launch_rays_t, dtype, detail, p.integration, v, p, frame, o, d, pxy, n, out, s);
 }
 
 hipError_t launch_jitter(const uint32_t* pxy, long long n, uint32_t frame, uint32_t seed,

@@ -1,0 +1,467 @@
+// Serving: persistent batched render + resolve kernels, the HIP executor
+// behind the scheduler, and the cloud_serve_* C ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/cloud.h"
+#include "cloud_device.h"
+#include "cloud_launch.h"
+#include "cloud_prepare.h"
+#include "serve_core.h"
+#include "serve_types.h"
+
+namespace cloud {
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Index of the request owning global tile t (requests are in tile order).
+__device__ __forceinline__ int find_item(const ServeTable* tab, int n_items, int t) {
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab->items[mid].tile_begin <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Persistent render over every tile of every request in the batch. The tile
+// sequence (requests back to back, each in super-tile order) is cut into 8
+// contiguous ranges, one per XCD (workgroups are dealt to XCDs round-robin,
+// so blockIdx % 8 names the XCD a workgroup most likely runs on); a
+// workgroup drains its own range first, then helps the others, so neighbouring
+// tiles tend to share an L2. Every workgroup leaves once all ranges are empty.
+template <int DT, int LAYOUT, bool DETAIL>
+__global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol, ServeTable* tab) {
+  unsigned int* counters = tab->counters;
+  __shared__ int s_tile;
+  const int total = tab->total_tiles, n_items = tab->n_items, S = tab->supertile;
+  const int home = blockIdx.x & 7;
+  for (int probe = 0; probe < 8;) {
+    const int q = (home + probe) & 7;
+    const int b = (int)(((long long)total * q) >> 3), e = (int)(((long long)total * (q + 1)) >> 3);
+    if (threadIdx.x == 0) s_tile = b + (int)atomicAdd(&counters[q], 1u);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(s_tile);
+    __syncthreads();
+    if (t >= e) {
+      ++probe;
+      continue;
+    }
+    const int i = find_item(tab, n_items, t);
+    const ServeItem& it = tab->items[i];
+    int tx, ty;
+    supertile(t - it.tile_begin, it.tiles_x, it.tiles_y, S, tx, ty);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int px = tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    if (px < it.width && py < it.height) {
+      float dx, dy, dz;
+      camera_dir(it.cam, px, py, it.width, it.height, dx, dy, dz);
+      const float j =
+          it.prm.jitter ? jitter_offset((uint32_t)px, (uint32_t)py, it.frame, it.prm.seed) : 0.5f;
+      const RayResult r = march<DT, LAYOUT, DETAIL, false>(vol, it.prm, it.cam.pos[0],
+                                                           it.cam.pos[1], it.cam.pos[2], dx, dy,
+                                                           dz, j);
+      static_cast<float4*>(it.cur)[(size_t)py * it.width + px] = make_float4(r.r, r.g, r.b, r.a);
+    }
+  }
+}
+
+// Batched temporal resolve: every tile of every request, grid-strided. A
+// request without usable history copies its frame; otherwise the 3x3
+// neighbourhood clamp and blend of the single-frame resolve. The result goes
+// to the stream's history and to the caller's output.
+__global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* tab) {
+  __shared__ float4 tile[18][18];
+  const int total = tab->total_tiles, n_items = tab->n_items;
+  const float blend = tab->blend;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int i = find_item(tab, n_items, t);
+    const ServeItem& it = tab->items[i];
+    const int W = it.width, H = it.height;
+    const int k = t - it.tile_begin;
+    const int tyi = k / it.tiles_x, txi = k - tyi * it.tiles_x;
+    const int bx = txi * 16, by = tyi * 16;
+    const float4* cur = static_cast<const float4*>(it.cur);
+    float4* hist = static_cast<float4*>(it.hist);
+    float4* out = static_cast<float4*>(it.out);
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int px = bx + lx, py = by + ly;
+    const bool inside = px < W && py < H;
+    const size_t p = (size_t)py * W + px;
+    if (it.reset) {
+      if (inside) {
+        const float4 v = cur[p];
+        hist[p] = v;
+        out[p] = v;
+      }
+      continue;
+    }
+    for (int e = threadIdx.x; e < 18 * 18; e += 256) {
+      const int ey = e / 18, ex = e - ey * 18;
+      const int gx = min(max(bx + ex - 1, 0), W - 1);
+      const int gy = min(max(by + ey - 1, 0), H - 1);
+      tile[ey][ex] = cur[(size_t)gy * W + gx];
+    }
+    __syncthreads();
+    if (inside) {
+      const float4 c = tile[ly + 1][lx + 1];
+      float4 lo = c, hi = c;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const float4 v = tile[ly + dy][lx + dx];
+          lo.x = fminf(lo.x, v.x); lo.y = fminf(lo.y, v.y); lo.z = fminf(lo.z, v.z); lo.w = fminf(lo.w, v.w);
+          hi.x = fmaxf(hi.x, v.x); hi.y = fmaxf(hi.y, v.y); hi.z = fmaxf(hi.z, v.z); hi.w = fmaxf(hi.w, v.w);
+        }
+      }
+      float4 h = hist[p];
+      h.x = fminf(fmaxf(h.x, lo.x), hi.x);
+      h.y = fminf(fmaxf(h.y, lo.y), hi.y);
+      h.z = fminf(fmaxf(h.z, lo.z), hi.z);
+      h.w = fminf(fmaxf(h.w, lo.w), hi.w);
+      const float4 r = make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
+                                   fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w));
+      hist[p] = r;
+      out[p] = r;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// HIP executor
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Payload {
+  DevCamera cam;
+  DevParams prm;
+};
+
+typedef void (*RenderFn)(DevVolume, ServeTable*);
+
+template <int DT, int LAYOUT>
+RenderFn pick_l(bool detail) {
+  return detail ? serve_render_kernel<DT, LAYOUT, true> : serve_render_kernel<DT, LAYOUT, false>;
+}
+
+template <int DT>
+RenderFn pick_dt(int layout, bool detail) {
+  switch (layout) {
+    case LAYOUT_QUAD: return pick_l<DT, LAYOUT_QUAD>(detail);
+    case LAYOUT_OCT: return pick_l<DT, LAYOUT_OCT>(detail);
+    default: return pick_l<DT, LAYOUT_DENSE>(detail);
+  }
+}
+
+RenderFn pick(int dtype, int layout, bool detail) {
+  switch (dtype) {
+    case DT_F16: return pick_dt<DT_F16>(layout, detail);
+    case DT_BF16: return pick_dt<DT_BF16>(layout, detail);
+    default: return pick_dt<DT_F32>(layout, detail);
+  }
+}
+
+constexpr int kSlots = 2;
+
+class HipExecutor : public serve::Executor {
+ public:
+  HipExecutor(int device, const DevVolume& v, int dtype, int layout, float blend, bool graphs)
+      : device_(device), vol_(v), blend_(blend), graphs_(graphs) {
+    fn_ = pick(dtype, layout, v.detail != nullptr);
+  }
+
+  int init(std::string* msg) {
+    hipError_t e = hipSetDevice(device_);
+    if (e != hipSuccess) return err(e, msg);
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device_);
+    if (e != hipSuccess) return err(e, msg);
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn_),
+                                                     256, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 4;
+    render_blocks_ = cus * per_cu;
+    taa_blocks_ = cus * 4;
+    for (int s = 0; s < kSlots; ++s) {
+      if ((e = hipStreamCreateWithFlags(&stream_[s], hipStreamNonBlocking)) != hipSuccess) return err(e, msg);
+      if ((e = hipEventCreateWithFlags(&event_[s], hipEventDisableTiming)) != hipSuccess) return err(e, msg);
+      if ((e = hipHostMalloc(reinterpret_cast<void**>(&host_[s]), sizeof(ServeTable), hipHostMallocDefault)) != hipSuccess)
+        return err(e, msg);
+      std::memset(host_[s], 0, sizeof(ServeTable));
+      if ((e = hipMalloc(reinterpret_cast<void**>(&dev_[s]), sizeof(ServeTable))) != hipSuccess)
+        return err(e, msg);
+      if (graphs_ && (e = capture(s)) != hipSuccess) return err(e, msg);
+    }
+    return CLOUD_OK;
+  }
+
+  ~HipExecutor() override {
+    (void)hipSetDevice(device_);
+    for (int s = 0; s < kSlots; ++s) {
+      if (stream_[s]) (void)hipStreamSynchronize(stream_[s]);
+      if (exec_[s]) (void)hipGraphExecDestroy(exec_[s]);
+      if (graph_[s]) (void)hipGraphDestroy(graph_[s]);
+      if (dev_[s]) (void)hipFree(dev_[s]);
+      if (host_[s]) (void)hipHostFree(host_[s]);
+      if (event_[s]) (void)hipEventDestroy(event_[s]);
+      if (stream_[s]) (void)hipStreamDestroy(stream_[s]);
+    }
+  }
+
+  void thread_init() override { (void)hipSetDevice(device_); }
+
+  size_t stream_bytes(int w, int h) override {
+    return 2 * (((size_t)w * h * 16 + 255) & ~(size_t)255);
+  }
+
+  int alloc(size_t bytes, void** mem) override {
+    return hipMalloc(mem, bytes) == hipSuccess ? 0 : CLOUD_E_NOMEM;
+  }
+
+  void release(void* mem) override { (void)hipFree(mem); }
+
+  int launch(int slot, const std::vector<serve::Item>& items) override {
+    ServeTable* t = host_[slot];
+    int tile = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+      const serve::Item& r = items[i];
+      ServeItem& it = t->items[i];
+      Payload pl;
+      std::memcpy(&pl, r.payload.data(), sizeof pl);
+      it.cam = pl.cam;
+      it.prm = pl.prm;
+      it.width = r.width;
+      it.height = r.height;
+      it.tiles_x = (r.width + 15) / 16;
+      it.tiles_y = (r.height + 15) / 16;
+      it.tile_begin = tile;
+      it.reset = r.reset_history ? 1 : 0;
+      it.frame = r.frame;
+      const size_t half = stream_bytes(r.width, r.height) / 2;
+      it.cur = r.stream_mem;
+      it.hist = static_cast<char*>(r.stream_mem) + half;
+      it.out = r.out;
+      tile += it.tiles_x * it.tiles_y;
+    }
+    std::memset(t->counters, 0, sizeof t->counters);
+    t->total_tiles = tile;
+    t->n_items = (int)items.size();
+    t->blend = blend_;
+    t->supertile = tuning().supertile;
+    hipError_t e;
+    if (graphs_) {
+      e = hipGraphLaunch(exec_[slot], stream_[slot]);
+    } else {
+      e = enqueue(slot);
+    }
+    if (e == hipSuccess) e = hipEventRecord(event_[slot], stream_[slot]);
+    return e == hipSuccess ? 0 : CLOUD_E_HIP;
+  }
+
+  int query(int slot) override {
+    const hipError_t e = hipEventQuery(event_[slot]);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return CLOUD_E_HIP;
+  }
+
+ private:
+  hipError_t enqueue(int slot) {
+    // table (with zeroed counters) -> persistent render -> batched resolve
+    hipError_t e = hipMemcpyAsync(dev_[slot], host_[slot], sizeof(ServeTable),
+                                  hipMemcpyHostToDevice, stream_[slot]);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn_, dim3(render_blocks_), dim3(256), 0, stream_[slot], vol_, dev_[slot]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(serve_taa_kernel, dim3(taa_blocks_), dim3(256), 0, stream_[slot], dev_[slot]);
+    return hipGetLastError();
+  }
+
+  hipError_t capture(int slot) {
+    hipError_t e = hipStreamBeginCapture(stream_[slot], hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t le = enqueue(slot);
+    e = hipStreamEndCapture(stream_[slot], &graph_[slot]);
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    return hipGraphInstantiate(&exec_[slot], graph_[slot], nullptr, nullptr, 0);
+  }
+
+  static int err(hipError_t e, std::string* msg) {
+    *msg = std::string("HIP: ") + hipGetErrorString(e);
+    return CLOUD_E_HIP;
+  }
+
+  int device_;
+  DevVolume vol_;
+  float blend_;
+  bool graphs_;
+  RenderFn fn_ = nullptr;
+  int render_blocks_ = 0, taa_blocks_ = 0;
+  hipStream_t stream_[kSlots] = {};
+  hipEvent_t event_[kSlots] = {};
+  ServeTable* host_[kSlots] = {};
+  ServeTable* dev_[kSlots] = {};
+  hipGraph_t graph_[kSlots] = {};
+  hipGraphExec_t exec_[kSlots] = {};
+};
+
+}  // namespace
+}  // namespace cloud
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+struct cloud_server {
+  cloud_volume volume;
+  std::unique_ptr<cloud::HipExecutor> ex;
+  std::unique_ptr<cloud::serve::Scheduler> sched;
+};
+
+using namespace cloud;
+
+extern "C" {
+
+int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg,
+                       cloud_server** out) {
+  try {
+    clear_error();
+    if (!out) return fail(CLOUD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(CLOUD_E_INVALID, "config is NULL");
+    if (cfg->max_batch < 1 || cfg->max_batch > kMaxBatch)
+      return fail(CLOUD_E_INVALID, "max_batch must be in [1, 64]");
+    if (cfg->max_queue < 1) return fail(CLOUD_E_INVALID, "max_queue must be >= 1");
+    if (!std::isfinite(cfg->taa_blend) || !(cfg->taa_blend > 0.0f) || cfg->taa_blend > 1.0f)
+      return fail(CLOUD_E_INVALID, "taa_blend must be in (0, 1]");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
+      return fail(CLOUD_E_INVALID, "no such device");
+    if (hipSetDevice(cfg->device) != hipSuccess) return fail(CLOUD_E_HIP, "hipSetDevice failed");
+    DevVolume v;
+    int dtype, rc;
+    if ((rc = prepare_volume(shared, &v, &dtype))) return rc;
+    auto srv = std::make_unique<cloud_server>();
+    srv->volume = *shared;
+    srv->ex = std::make_unique<HipExecutor>(cfg->device, v, dtype, shared->layout, cfg->taa_blend,
+                                            cfg->use_graphs != 0);
+    std::string msg;
+    if ((rc = srv->ex->init(&msg))) return fail(rc, msg);
+    serve::Config sc;
+    sc.budget_bytes = cfg->hbm_budget_bytes;
+    sc.max_batch = cfg->max_batch;
+    sc.max_queue = cfg->max_queue;
+    sc.depth = kSlots;
+    srv->sched = std::make_unique<serve::Scheduler>(srv->ex.get(), sc);
+    *out = srv.release();
+    return CLOUD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(CLOUD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(CLOUD_E_INVALID, "internal error");
+  }
+}
+
+int cloud_serve_submit(cloud_server* srv, uint64_t stream_id, const cloud_camera* camera,
+                       const cloud_params* params, int32_t width, int32_t height,
+                       uint32_t frame_index, float* out_rgba, uint64_t* request_id) {
+  try {
+    clear_error();
+    if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
+    if (!request_id) return fail(CLOUD_E_INVALID, "request_id is NULL");
+    int rc = check_image(width, height, 1);
+    if (rc) return rc;
+    Payload pl;
+    if ((rc = prepare_camera(camera, width, height, &pl.cam))) return rc;
+    if ((rc = prepare_params(params, &srv->volume, &pl.prm))) return rc;
+    if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
+      return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
+    if ((rc = check_span(out_rgba, (size_t)width * height * 16, "out_rgba"))) return rc;
+    std::vector<unsigned char> bytes(sizeof pl);
+    std::memcpy(bytes.data(), &pl, sizeof pl);
+    std::string msg;
+    rc = srv->sched->submit(stream_id, width, height, frame_index, out_rgba, std::move(bytes),
+                            request_id, &msg);
+    if (rc) return fail(rc, msg);
+    return CLOUD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(CLOUD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(CLOUD_E_INVALID, "internal error");
+  }
+}
+
+int cloud_serve_poll(cloud_server* srv, cloud_completion* out, int32_t max, int32_t* n_out) {
+  clear_error();
+  if (!srv || !n_out || (max > 0 && !out)) return fail(CLOUD_E_INVALID, "NULL argument");
+  std::vector<serve::Completion> tmp(max > 0 ? max : 0);
+  int n = 0;
+  srv->sched->poll(tmp.data(), max, &n);
+  for (int i = 0; i < n; ++i) {
+    out[i].request_id = tmp[i].request_id;
+    out[i].stream_id = tmp[i].stream_id;
+    out[i].status = tmp[i].status;
+    out[i].reserved = 0;
+    out[i].t_submit_ns = tmp[i].t_submit;
+    out[i].t_admit_ns = tmp[i].t_admit;
+    out[i].t_start_ns = tmp[i].t_start;
+    out[i].t_done_ns = tmp[i].t_done;
+  }
+  *n_out = n;
+  return CLOUD_OK;
+}
+
+int cloud_serve_wait(cloud_server* srv, int64_t timeout_ns) {
+  clear_error();
+  if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
+  return srv->sched->wait(timeout_ns);
+}
+
+int cloud_serve_stats(cloud_server* srv, cloud_serve_stats_t* out) {
+  clear_error();
+  if (!srv || !out) return fail(CLOUD_E_INVALID, "NULL argument");
+  const serve::Stats s = srv->sched->stats();
+  out->queued = s.queued;
+  out->admitted = s.admitted;
+  out->running = s.running;
+  out->completed = s.completed;
+  out->rejected = s.rejected;
+  out->cancelled = s.cancelled;
+  out->failed = s.failed;
+  out->streams = s.streams;
+  out->bytes_in_use = s.bytes_in_use;
+  out->batches = s.batches;
+  return CLOUD_OK;
+}
+
+int cloud_serve_close_stream(cloud_server* srv, uint64_t stream_id) {
+  clear_error();
+  if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
+  const int rc = srv->sched->close_stream(stream_id);
+  if (rc) return fail(rc, "unknown stream");
+  return CLOUD_OK;
+}
+
+int cloud_serve_destroy(cloud_server* srv) {
+  clear_error();
+  if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
+  srv->sched.reset();   // cancels queued requests, waits for in-flight batches
+  srv->ex.reset();
+  delete srv;
+  return CLOUD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// Device descriptor table of one serving batch (host and device view).
+//
+// The host fills a pinned copy per batch slot; the captured graph copies it
+// to the device and runs the persistent render kernel and the batched resolve
+// over every request in it. The work counters sit in the table, so the
+// per-batch copy also resets them (no memset node in the graph).
+#pragma once
+
+#include <stdint.h>
+
+#include "cloud_types.h"
+
+namespace cloud {
+
+constexpr int kMaxBatch = 64;   // requests per batch
+
+struct ServeItem {
+  DevCamera cam;
+  DevParams prm;
+  int width, height;
+  int tiles_x, tiles_y;
+  int tile_begin;               // first global tile of this request
+  int reset;                    // 1: no usable history, the frame is copied
+  uint32_t frame;
+  int pad;
+  void* cur;                    // [H][W] float4 scratch: this frame before resolve
+  void* hist;                   // [H][W] float4 history (stream state)
+  void* out;                    // [H][W] float4 caller output
+};
+
+struct ServeTable {
+  unsigned int counters[8];     // per-XCD render work counters
+  int total_tiles;
+  int n_items;
+  float blend;
+  int supertile;
+  ServeItem items[kMaxBatch];
+};
+
+}  // namespace cloud

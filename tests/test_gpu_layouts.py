@@ -1,0 +1,103 @@
+"""Packed volume layouts and lookup counting, through the C ABI.
+
+The quad and oct layouts hold the same texel values as the dense volume, so
+a render from a packed volume must equal the dense render bit for bit (and
+therefore match the oracle to the same tolerance). The lookup count must
+equal the oracle's count of the lookups it performs, up to the few samples
+whose density or early exit lands on the other side of zero or t_eps in
+float32 than in float64.
+"""
+
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import cloud as O
+from paper_1609_05344_amd import scenes
+from tests.helpers import FP32_TOL, HALF_TOL, max_err, oracle_volume, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import torch
+    import paper_1609_05344_amd as cf
+    assert torch.cuda.is_available()
+    cf.load()
+    return cf
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("layout", ["quad", "oct"])
+def test_packed_equals_dense(cf, dtype, layout):
+    w = scenes.workload("H")
+    say(f"{layout} {dtype}: H frame vs dense, bitwise")
+    sc = scenes.make_scene(w, dtype=dtype)
+    dense = cf.device_volume(sc)
+    packed = cf.cloud_volume_pack(dense, layout)
+    a = to_np(cf.cloud_render(dense, w.camera(5), w.params, 5, w.width, w.height))
+    b = to_np(cf.cloud_render(packed, w.camera(5), w.params, 5, w.width, w.height))
+    assert np.array_equal(a, b)
+    assert a[..., 3].max() > 0.5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("layout", ["quad", "oct"])
+def test_packed_small_volumes_vs_oracle(cf, dtype, layout):
+    say(f"{layout} {dtype}: C1 full frame and odd-sized volume vs oracle")
+    w = scenes.workload("C1", jitter=1)
+    tol = FP32_TOL if dtype == "f32" else HALF_TOL
+    sc = scenes.make_scene(w, dtype=dtype)
+    packed = cf.cloud_volume_pack(cf.device_volume(sc), layout)
+    got = to_np(cf.cloud_render(packed, w.camera(0), w.params, 2, 64, 64))
+    assert max_err(got, O.render(oracle_volume(sc), w.camera(0), w.params, 64, 64, frame=2)) < tol
+    # non-cubic, odd dims: exercises every clamped edge entry
+    rng = np.random.default_rng(3)
+    base = np.clip(rng.uniform(-0.5, 1.0, size=(5, 7, 3)), 0, 1)
+    st = scenes.quantise(base, dtype)
+    sc2 = scenes.Scene(w, st, scenes.decode(st, dtype))
+    packed2 = cf.cloud_volume_pack(cf.device_volume(sc2), layout)
+    cam = scenes.orbit_camera(1.2, 200.0, 35.0)
+    got = to_np(cf.cloud_render(packed2, cam, w.params, 1, 40, 30))
+    assert max_err(got, O.render(oracle_volume(sc2), cam, w.params, 40, 30, frame=1)) < tol
+
+
+def test_pack_errors(cf):
+    import torch
+    w = scenes.workload("C1")
+    dense = cf.device_volume(scenes.make_scene(w))
+    with pytest.raises(cf.CloudError):
+        cf.cloud_volume_pack(dense, "dense")
+    n = cf.cloud_volume_packed_bytes(dense, "oct")
+    assert n == 33 * 33 * 33 * 8 * 4
+    assert cf.cloud_volume_packed_bytes(dense, "quad") == 33 * 33 * 32 * 4 * 4
+    small = torch.empty((n // 2,), dtype=torch.uint8, device="cuda")
+    from paper_1609_05344_amd import _lib
+    import ctypes
+    out = _lib.cloud_volume()
+    rc = _lib.load().cloud_volume_pack(ctypes.byref(dense.struct), 2, small.data_ptr(), n // 2,
+                                       ctypes.byref(out), None)
+    assert rc == _lib.CLOUD_E_INVALID and "smaller" in _lib.last_error()
+
+
+@pytest.mark.parametrize("name,npix", [("C1", None), ("H", None)])
+def test_lookup_count_matches_oracle(cf, name, npix):
+    w = scenes.workload(name)
+    say(f"lookup count {name}")
+    sc = scenes.make_scene(w)
+    W, H = (w.width, w.height) if name == "C1" else (320, 180)
+    got = int(to_np(cf.cloud_count_lookups(cf.device_volume(sc), w.camera(1), w.params, 1, W, H))[0])
+    _, want = O.render(oracle_volume(sc), w.camera(1), w.params, W, H, frame=1, return_lookups=True)
+    assert want > 0
+    assert abs(got - want) <= 2e-3 * want, (got, want)
+    packed = cf.cloud_volume_pack(cf.device_volume(sc), "oct")
+    got2 = int(to_np(cf.cloud_count_lookups(packed, w.camera(1), w.params, 1, W, H))[0])
+    assert got2 == got

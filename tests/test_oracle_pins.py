@@ -322,6 +322,7 @@ def test_jitter_mean_matches_closed_form():
 # ---------------------------------------------------------------------------
 
 def test_hash_known_answers():
+    jit = []
     with open(os.path.join(HERE, "golden", "pcg_kat.txt")) as f:
         for line in f:
             if line.startswith("#"):
@@ -329,9 +330,16 @@ def test_hash_known_answers():
             parts = line.split()
             if parts[0] == "pcg":
                 assert O.pcg_hash(int(parts[1])) == int(parts[2])
+                assert int(O.pcg_hash(np.array([int(parts[1])], dtype=np.uint64))[0]) == int(parts[2])
             else:
                 px, py, fr, sd, bits = map(int, parts[1:])
                 assert O.jitter_offset(px, py, fr, sd) == bits * 2.0 ** -24
+                jit.append((px, py, fr, sd, bits))
+    # the array path (used by render) gives the same offsets
+    for fr, sd in {(r[2], r[3]) for r in jit}:
+        rows = [r for r in jit if r[2] == fr and r[3] == sd]
+        got = O.jitter_offset(np.array([r[0] for r in rows]), np.array([r[1] for r in rows]), fr, sd)
+        assert np.array_equal(got, np.array([r[4] for r in rows]) * 2.0 ** -24)
 
 
 def test_hash_scalar_matches_vector_and_is_bijective_on_a_range():

@@ -84,9 +84,7 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
     (submit -> done) over the measured window."""
     import numpy as np
     sc = scenes.make_scene(w, dtype=dtype)
-    vol = cf.device_volume(sc)
-    if layout != "dense":
-        vol = cf.cloud_volume_pack(vol, layout)
+    vol = cf.device_volume(sc, layout=layout, occupancy=True)
     W, H = w.width, w.height
     outs = [torch.empty((H, W, 4), device="cuda") for _ in range(n_streams)]
     frame = [0] * n_streams
@@ -120,6 +118,75 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
             "frames": len(lat), "batches": st["batches"]}
 
 
+def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: float = 1.0,
+                   n_streams: int = 64, seed: int = 5344, ring: int = 4,
+                   budget_bytes: int = 64 << 30) -> dict:
+    """Open-loop serving load: n_streams camera streams, each with a
+    resolution from {640x360, 1280x720, 1920x1080, 3840x2160} and a step
+    count from {8, 16, 32, 128} drawn once; Poisson arrivals at rate_hz in
+    total, each for a uniformly chosen stream; a shared FP16 256^3 volume.
+    Latency runs from the scheduled arrival to completion."""
+    import numpy as np
+    from dataclasses import replace
+    rng = np.random.default_rng(seed)
+    sizes = [(640, 360), (1280, 720), (1920, 1080), (3840, 2160)]
+    steps = [8, 16, 32, 128]
+    spec = [(sizes[rng.integers(4)], steps[rng.integers(4)]) for _ in range(n_streams)]
+    w = scenes.workload("C2")
+    vol = cf.device_volume(scenes.make_scene(w, dtype="f16"), layout="oct", occupancy=True)
+    bufs = [[torch.empty((h, wd, 4), device="cuda") for _ in range(ring)] for (wd, h), _ in spec]
+    free = [list(range(ring)) for _ in range(n_streams)]
+    frame = [0] * n_streams
+    params = [replace(w.params, steps=st) for _, st in spec]
+    inflight = {}
+    lat, done_t = [], []
+    busy = nobuf = 0
+    gaps = rng.exponential(1.0 / rate_hz, size=int(rate_hz * (warm_s + seconds) * 1.5) + 16)
+    which = rng.integers(n_streams, size=gaps.size)
+    with cf.Server(vol, budget_bytes=budget_bytes, max_batch=64, max_queue=4096) as srv:
+        t0 = time.monotonic()
+        t_arr = t0 + np.cumsum(gaps)
+        k, t_end = 0, t0 + warm_s + seconds
+        while True:
+            now = time.monotonic()
+            if now >= t_end:
+                break
+            while k < t_arr.size and t_arr[k] <= now:
+                s = int(which[k])
+                if free[s]:
+                    b = free[s].pop()
+                    (wd, h), _ = spec[s]
+                    rc, rid = srv.try_submit(s, w.camera(frame[s], view=s % 8), params[s], wd, h,
+                                             frame[s], bufs[s][b])
+                    if rc == 0:
+                        inflight[rid] = (s, b, t_arr[k])
+                        frame[s] += 1
+                    else:
+                        free[s].append(b)
+                        busy += 1
+                else:
+                    nobuf += 1
+                k += 1
+            for c in srv.poll(512):
+                s, b, ta = inflight.pop(c["request_id"])
+                free[s].append(b)
+                if ta >= t0 + warm_s:
+                    lat.append(c["t_done_ns"] * 1e-9 - ta)
+                    done_t.append(c["t_done_ns"] * 1e-9)
+            nxt = t_arr[k] if k < t_arr.size else t_end
+            srv.wait(max(0.0, min(nxt - time.monotonic(), 0.002)))
+        backlog = len(inflight)
+        st = srv.stats()
+    offered = float(np.sum((t_arr >= t0 + warm_s) & (t_arr < t_end)))
+    lat_ms = np.array(lat) * 1e3
+    return {"rate_hz": rate_hz, "seconds": seconds, "offered": int(offered),
+            "completed": len(lat), "completed_per_s": round(len(lat) / seconds, 1),
+            "latency_p50_ms": round(float(np.percentile(lat_ms, 50)), 2) if lat else None,
+            "latency_p99_ms": round(float(np.percentile(lat_ms, 99)), 2) if lat else None,
+            "rejected_busy": busy, "dropped_no_buffer": nobuf, "backlog_at_end": backlog,
+            "batches": st["batches"], "streams": n_streams}
+
+
 # ---------------------------------------------------------------------------
 # GPU run
 # ---------------------------------------------------------------------------
@@ -137,6 +204,12 @@ def main():
     ap.add_argument("--served-dtype", default="f16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--served-layout", default="oct", choices=["dense", "quad", "oct"])
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-occupancy", action="store_true",
+                    help="render without the exact empty-space-skipping bitmap")
+    ap.add_argument("--serve-poisson", default="",
+                    help="comma-separated total arrival rates (req/s): run only the open-loop "
+                         "64-stream serving load at each rate and print one JSON line")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-frames", type=int, default=36)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -148,6 +221,19 @@ def main():
               "(frames and streams are independent; see the sharding notes in DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.serve_poisson:
+        import torch
+        import paper_1609_05344_amd as cf
+        from paper_1609_05344_amd import scenes
+        runs = [served_poisson(cf, scenes, torch, float(r), args.serve_seconds)
+                for r in args.serve_poisson.split(",")]
+        print(json.dumps({"metric": "served frame latency p50/p99, open-loop Poisson arrivals",
+                          "unit": "ms", "config": {"workload": "64 streams, resolutions in "
+                          "{640x360,1280x720,1920x1080,3840x2160}, steps in {8,16,32,128}, "
+                          "shared f16 256^3 (oct layout, occupancy), TAA per stream"},
+                          "runs": runs}), flush=True)
+        return
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -164,9 +250,7 @@ def main():
     dev = torch.device("cuda:0")
     w = scenes.workload(args.workload)
     sc = scenes.make_scene(w, dtype=args.dtype)
-    vol = cf.device_volume(sc, dev)
-    if args.layout != "dense":
-        vol = cf.cloud_volume_pack(vol, args.layout)
+    vol = cf.device_volume(sc, dev, layout=args.layout, occupancy=not args.no_occupancy)
     W, H, p = w.width, w.height, w.params
     total = args.warmup + args.steps
 
@@ -234,6 +318,7 @@ def main():
                    "primary_steps": p.steps, "light_steps": p.light_steps, "jitter": "per-pixel",
                    "integration": "analytic", "taa_blend": w.taa_blend,
                    "volume": f"{w.volume.n}^3 {args.dtype}", "layout": args.layout,
+                   "occupancy_skip": not args.no_occupancy,
                    "lookups_per_frame": round(lk_frame)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": MI355X_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / MI355X_HBM_GBPS, 4),

@@ -80,6 +80,12 @@ enum { CLOUD_F32 = 0, CLOUD_F16 = 1, CLOUD_BF16 = 2 };
  *  layout  CLOUD_LAYOUT_* of base (a packed base is 16-byte aligned and
  *          normally made by cloud_volume_pack); nx, ny, nz always count
  *          texels. The detail volume is always dense.
+ *  occupancy       device, optional (NULL = none): a bitmap made by
+ *          cloud_volume_occupancy, one bit per brick of 2^occupancy_log2
+ *          texels per axis, clear when every texel a trilinear footprint
+ *          starting in that brick can touch is zero. A lookup in a clear
+ *          brick is exactly zero, so it is answered without reading the
+ *          volume; results are bitwise identical with and without it.
  *  Requirements: n* >= 2, dn* >= 2 when detail is set, fewer than 2^24
  *  entries per plane, box_max > box_min on every axis,
  *  0 <= detail_weight < 1, detail_tiling > 0, detail values in [0, 1].
@@ -96,6 +102,8 @@ typedef struct {
   float box_min[3];
   float box_max[3];
   int32_t layout;
+  const uint32_t* occupancy;
+  int32_t occupancy_log2;
 } cloud_volume;
 
 /* Pinhole camera: rays leave pos through pixel centres; vfov_deg is the
@@ -208,6 +216,22 @@ int cloud_volume_packed_bytes(const cloud_volume* dense, int32_t layout,
  * packed and dense volumes are identical. */
 int cloud_volume_pack(const cloud_volume* dense, int32_t layout, void* dst,
                       uint64_t dst_bytes, cloud_volume* packed, void* hip_stream);
+
+/* Occupancy bitmap of the dense volume's base, for exact empty-space
+ * skipping (see cloud_volume.occupancy). The brick size is the smallest
+ * power of two >= 4 texels for which the bitmap has at most 32768 bits, so
+ * that the kernels can keep it in LDS. *bytes / *log2_brick receive the
+ * bitmap size and brick size. */
+int cloud_volume_occupancy_bytes(const cloud_volume* dense, uint64_t* bytes,
+                                 int32_t* log2_brick);
+
+/* Enqueues the build of that bitmap into dst (device, caller-owned, at
+ * least cloud_volume_occupancy_bytes bytes, 4-byte aligned) and fills
+ * *with_occupancy with the volume's descriptor pointing at it (any layout of
+ * the same texels may then use it). Bit b of word w is brick w*32+b, bricks
+ * ordered x fastest. */
+int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t dst_bytes,
+                           cloud_volume* with_occupancy, void* hip_stream);
 
 /* Launch-shape knob, process-wide, for tuning and benchmarking; results do
  * not depend on it. Keys: "supertile" (0..64, default 4) -- the render walks

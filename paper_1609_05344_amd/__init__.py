@@ -18,6 +18,7 @@ from ._lib import (  # noqa: F401
     cloud_render_views,
     cloud_taa_resolve,
     cloud_tune,
+    cloud_volume_occupancy,
     cloud_volume_pack,
     cloud_volume_packed_bytes,
     last_error,
@@ -25,8 +26,9 @@ from ._lib import (  # noqa: F401
 )
 
 
-def device_volume(scene, device="cuda"):
-    """Upload a seeded scene's stored volumes (see scenes.make_scene)."""
+def device_volume(scene, device="cuda", layout: str = "dense", occupancy: bool = False):
+    """Upload a seeded scene's stored volumes (see scenes.make_scene),
+    optionally with an occupancy bitmap and in a packed layout."""
     import numpy as np
     import torch
 
@@ -42,5 +44,10 @@ def device_volume(scene, device="cuda"):
     base, det = up(scene.base_stored), up(scene.detail_stored)
     dtype = {np.dtype(np.float32): "f32", np.dtype(np.float16): "f16",
              np.dtype(np.uint16): "bf16"}[scene.base_stored.dtype]
-    return Volume(base, det, dtype=dtype, detail_weight=w.params.detail_weight,
-                  detail_tiling=w.params.detail_tiling)
+    vol = Volume(base, det, dtype=dtype, detail_weight=w.params.detail_weight,
+                 detail_tiling=w.params.detail_tiling)
+    if occupancy:
+        vol = cloud_volume_occupancy(vol)
+    if layout != "dense":
+        vol = cloud_volume_pack(vol, layout)
+    return vol

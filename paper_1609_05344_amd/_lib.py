@@ -39,6 +39,7 @@ class cloud_volume(ctypes.Structure):
         ("detail", c_void_p), ("dnx", c_int32), ("dny", c_int32), ("dnz", c_int32),
         ("ddtype", c_int32), ("detail_weight", c_float), ("detail_tiling", c_float),
         ("box_min", c_float * 3), ("box_max", c_float * 3), ("layout", c_int32),
+        ("occupancy", c_void_p), ("occupancy_log2", c_int32),
     ]
 
 
@@ -81,6 +82,12 @@ def load():
     lib.cloud_jitter_offsets.argtypes = [c_void_p, c_int64, c_uint32, c_uint32, c_void_p, c_void_p]
     lib.cloud_check_buffer.argtypes = [c_void_p, c_uint64]
     lib.cloud_tune.argtypes = [c_char_p, c_int32]
+    lib.cloud_volume_occupancy_bytes.argtypes = [POINTER(cloud_volume), POINTER(c_uint64),
+                                                 POINTER(c_int32)]
+    lib.cloud_volume_occupancy.argtypes = [POINTER(cloud_volume), c_void_p, c_uint64,
+                                           POINTER(cloud_volume), c_void_p]
+    lib.cloud_volume_occupancy_bytes.restype = c_int
+    lib.cloud_volume_occupancy.restype = c_int
     lib.cloud_count_lookups.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera),
                                         POINTER(cloud_params), c_uint32, c_int32, c_int32,
                                         c_void_p, c_void_p]
@@ -253,7 +260,27 @@ def cloud_volume_pack(volume: Volume, layout: str, stream=None) -> "Volume":
     out = Volume.__new__(Volume)
     out.base, out.detail, out.dtype = buf, volume.detail, volume.dtype
     out.dense = volume
+    out.occupancy = getattr(volume, "occupancy", None)
     out.struct = packed
+    return out
+
+
+def cloud_volume_occupancy(volume: Volume, stream=None) -> "Volume":
+    """The same (dense) volume with an occupancy bitmap attached (a new device
+    buffer owned by the returned Volume); pack it afterwards to keep both."""
+    import torch
+    nbytes, lg = c_uint64(0), c_int32(0)
+    check(load().cloud_volume_occupancy_bytes(ctypes.byref(volume.struct), ctypes.byref(nbytes),
+                                              ctypes.byref(lg)))
+    buf = torch.empty((max(int(nbytes.value) // 4, 1),), dtype=torch.int32, device=volume.base.device)
+    withocc = cloud_volume()
+    check(load().cloud_volume_occupancy(ctypes.byref(volume.struct), _ptr(buf), int(nbytes.value),
+                                        ctypes.byref(withocc), _stream(stream)))
+    out = Volume.__new__(Volume)
+    out.base, out.detail, out.dtype = volume.base, volume.detail, volume.dtype
+    out.dense = volume
+    out.occupancy = buf
+    out.struct = withocc
     return out
 
 

@@ -77,6 +77,27 @@ int volume_layout_bytes(const cloud_volume* v, int layout, size_t* bytes) {
   return CLOUD_OK;
 }
 
+// Brick counts of an occupancy bitmap with bricks of 2^lg texels.
+static void occupancy_dims(const cloud_volume* v, int lg, int* nbx, int* nby, int* nbz) {
+  *nbx = ((v->nx - 1) >> lg) + 1;
+  *nby = ((v->ny - 1) >> lg) + 1;
+  *nbz = ((v->nz - 1) >> lg) + 1;
+}
+
+static int occupancy_words(int nbx, int nby, int nbz) {
+  return (int)(((long long)nbx * nby * nbz + 31) / 32);
+}
+
+// Smallest brick (>= 4 texels) whose bitmap fits the kernels' LDS budget.
+static int occupancy_log2(const cloud_volume* v) {
+  for (int lg = 2; lg < 16; ++lg) {
+    int a, b, c;
+    occupancy_dims(v, lg, &a, &b, &c);
+    if (occupancy_words(a, b, c) <= kOccupancyWords) return lg;
+  }
+  return 16;
+}
+
 int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
   if (!v) return fail(CLOUD_E_INVALID, "volume is NULL");
   size_t bytes = 0;
@@ -133,6 +154,24 @@ int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
       *dof[k] = (float)(-(double)v->box_min[k] * sc - 0.5);
     }
     d.detail_weight = v->detail_weight;
+  }
+  d.occ = nullptr;
+  if (v->occupancy) {
+    if (v->occupancy_log2 < 0 || v->occupancy_log2 > 15)
+      return fail(CLOUD_E_INVALID, "occupancy_log2 must be in [0, 15]");
+    int nbx, nby, nbz;
+    occupancy_dims(v, v->occupancy_log2, &nbx, &nby, &nbz);
+    const int words = occupancy_words(nbx, nby, nbz);
+    if (words > kOccupancyWords)
+      return fail(CLOUD_E_INVALID, "occupancy bitmap exceeds 32768 bricks; use a larger brick");
+    if (reinterpret_cast<uintptr_t>(v->occupancy) % 4)
+      return fail(CLOUD_E_INVALID, "occupancy must be 4-byte aligned");
+    if ((rc = check_span(v->occupancy, (size_t)words * 4, "occupancy"))) return rc;
+    d.occ = v->occupancy;
+    d.occ_lg = v->occupancy_log2;
+    d.occ_nbx = nbx;
+    d.occ_nby = nby;
+    d.occ_words = words;
   }
   *out = d;
   *dtype = v->dtype;
@@ -399,6 +438,52 @@ int cloud_taa_resolve(const float* current, const float* history, float* out, in
   hipError_t e = launch_taa(current, history, out, width, height, blend, copy,
                             static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_volume_occupancy_bytes(const cloud_volume* dense, uint64_t* bytes, int32_t* log2_brick) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (!bytes || !log2_brick) return fail(CLOUD_E_INVALID, "NULL output");
+  size_t b = 0;
+  const int rc = volume_layout_bytes(dense, CLOUD_LAYOUT_DENSE, &b);
+  if (rc) return rc;
+  const int lg = occupancy_log2(dense);
+  int nbx, nby, nbz;
+  occupancy_dims(dense, lg, &nbx, &nby, &nbz);
+  *bytes = (uint64_t)occupancy_words(nbx, nby, nbz) * 4;
+  *log2_brick = lg;
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t dst_bytes,
+                           cloud_volume* with_occupancy, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (!dense) return fail(CLOUD_E_INVALID, "volume is NULL");
+  if (!with_occupancy) return fail(CLOUD_E_INVALID, "with_occupancy is NULL");
+  if (dense->layout != CLOUD_LAYOUT_DENSE) return fail(CLOUD_E_INVALID, "source volume must be dense");
+  cloud_volume src = *dense;
+  src.occupancy = nullptr;   // the source's own bitmap (if any) is not needed
+  DevVolume v;
+  int dtype, rc;
+  if ((rc = prepare_volume(&src, &v, &dtype))) return rc;
+  const int lg = occupancy_log2(dense);
+  int nbx, nby, nbz;
+  occupancy_dims(dense, lg, &nbx, &nby, &nbz);
+  const size_t need = (size_t)occupancy_words(nbx, nby, nbz) * 4;
+  if (dst_bytes < need) return fail(CLOUD_E_INVALID, "dst is smaller than the bitmap");
+  if (reinterpret_cast<uintptr_t>(dst) % 4) return fail(CLOUD_E_INVALID, "dst must be 4-byte aligned");
+  if ((rc = check_span(dst, need, "dst"))) return rc;
+  hipError_t e = launch_occupancy(dense->base, (int)dtype_size(dtype), dense->nx, dense->ny,
+                                  dense->nz, lg, nbx, nby, nbz, dst,
+                                  static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("occupancy launch: ") + hipGetErrorString(e));
+  *with_occupancy = *dense;
+  with_occupancy->occupancy = dst;
+  with_occupancy->occupancy_log2 = lg;
   return CLOUD_OK;
   CLOUD_GUARD_END
 }

@@ -22,6 +22,20 @@ constexpr int kLightUnroll = CLOUD_LIGHT_UNROLL;
 #ifndef CLOUD_PREFETCH
 #define CLOUD_PREFETCH 0
 #endif
+// A lookup in an empty brick is exactly zero. Either it branches around the
+// fetch (CLOUD_OCC_SELECT 0), or it keeps the fetch in line but points it at
+// entry 0 -- a line every wave shares, so it costs no volume traffic -- and
+// selects 0 (CLOUD_OCC_SELECT 1), which keeps the light march's fetches in
+// flight together.
+#ifndef CLOUD_OCC_SELECT
+#define CLOUD_OCC_SELECT 1
+#endif
+#if CLOUD_OCC_SELECT
+#define CLOUD_SKIP_DEAD(live) ((void)0)
+#else
+#define CLOUD_SKIP_DEAD(live) \
+  if (!(live)) return 0.0f
+#endif
 
 // PCG-RXS-M-XS 32-bit hash (Jarzynski and Olano, JCGT 2020).
 __device__ __forceinline__ uint32_t pcg(uint32_t v) {
@@ -80,6 +94,33 @@ __device__ __forceinline__ void split_coord(float f, int n, float& w, int& k) {
 }
 
 // ---------------------------------------------------------------------------
+// Occupancy: one bit per brick, staged in LDS by every kernel that samples
+// ---------------------------------------------------------------------------
+
+static __shared__ uint32_t s_occupancy[kOccupancyWords];
+
+// Copies the volume's occupancy bitmap (if any) into LDS. Every thread of the
+// workgroup must call it before sampling (it ends with a barrier).
+__device__ __forceinline__ void stage_occupancy(const DevVolume& v) {
+  if (v.occ) {
+    for (int i = threadIdx.x; i < v.occ_words; i += blockDim.x) s_occupancy[i] = v.occ[i];
+  }
+  __syncthreads();
+}
+
+// False when every texel a footprint with corner k can touch is zero, so the
+// trilinear lookup is exactly 0 (k in [-1, n] per axis; the clamp maps it to
+// the brick holding the texels the lookup reads).
+__device__ __forceinline__ bool occupied(const DevVolume& v, int kx, int ky, int kz) {
+  if (!v.occ) return true;
+  const int bx = min(max(kx, 0), v.nx - 1) >> v.occ_lg;
+  const int by = min(max(ky, 0), v.ny - 1) >> v.occ_lg;
+  const int bz = min(max(kz, 0), v.nz - 1) >> v.occ_lg;
+  const int b = (bz * v.occ_nby + by) * v.occ_nbx + bx;
+  return (s_occupancy[b >> 5] >> (b & 31)) & 1u;
+}
+
+// ---------------------------------------------------------------------------
 // Base-volume trilinear lookup with clamp-to-edge, x then y then z
 // ---------------------------------------------------------------------------
 
@@ -95,18 +136,23 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
     split_coord(fx, v.nx, wx, kx);
     split_coord(fy, v.ny, wy, ky);
     split_coord(fz, v.nz, wz, kz);
+    const bool live = occupied(v, kx, ky, kz);
+    CLOUD_SKIP_DEAD(live);
     const int xa = min(max(kx, 0), v.nx - 1), xb = min(max(kx + 1, 0), v.nx - 1);
     const int ya = min(max(ky, 0), v.ny - 1), yb = min(max(ky + 1, 0), v.ny - 1);
     const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
     // indices stay below 2^31 and plane < 2^24 (checked on the host), so the
-    // 24-bit multiplies are exact
+    // 24-bit multiplies are exact; a dead lookup reads texel 0 instead
     const int ra = __umul24(ya, v.row), rb = __umul24(yb, v.row);
     const int pa = __umul24(za, v.plane), pb = __umul24(zb, v.plane);
-    const float c00 = lerp(texel<DT>(v.base, pa + ra + xa), texel<DT>(v.base, pa + ra + xb), wx);
-    const float c10 = lerp(texel<DT>(v.base, pa + rb + xa), texel<DT>(v.base, pa + rb + xb), wx);
-    const float c01 = lerp(texel<DT>(v.base, pb + ra + xa), texel<DT>(v.base, pb + ra + xb), wx);
-    const float c11 = lerp(texel<DT>(v.base, pb + rb + xa), texel<DT>(v.base, pb + rb + xb), wx);
-    return lerp(lerp(c00, c10, wy), lerp(c01, c11, wy), wz);
+    const int i0 = live ? pa + ra : 0, i1 = live ? pa + rb : 0;
+    const int i2 = live ? pb + ra : 0, i3 = live ? pb + rb : 0;
+    const int x0 = live ? xa : 0, x1 = live ? xb : 0;
+    const float c00 = lerp(texel<DT>(v.base, i0 + x0), texel<DT>(v.base, i0 + x1), wx);
+    const float c10 = lerp(texel<DT>(v.base, i1 + x0), texel<DT>(v.base, i1 + x1), wx);
+    const float c01 = lerp(texel<DT>(v.base, i2 + x0), texel<DT>(v.base, i2 + x1), wx);
+    const float c11 = lerp(texel<DT>(v.base, i3 + x0), texel<DT>(v.base, i3 + x1), wx);
+    return live ? lerp(lerp(c00, c10, wy), lerp(c01, c11, wy), wz) : 0.0f;
   }
 };
 
@@ -126,9 +172,12 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
     split_coord(fx, v.nx, wx, kx);
     split_coord(fy, v.ny, wy, ky);
     split_coord(fz, v.nz, wz, kz);
+    const bool live = occupied(v, kx, ky, kz);
+    CLOUD_SKIP_DEAD(live);
     const int e = packed_xy(v, kx, ky);
     const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
-    const int ea = __umul24(za, v.plane) + e, eb = __umul24(zb, v.plane) + e;
+    const int ea = live ? __umul24(za, v.plane) + e : 0;
+    const int eb = live ? __umul24(zb, v.plane) + e : 0;
     float a0, a1, a2, a3, b0, b1, b2, b3;
     if constexpr (DT == DT_F32) {
       const float4* q = static_cast<const float4*>(v.base);
@@ -145,7 +194,7 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
     }
     const float c0 = lerp(lerp(a0, a1, wx), lerp(a2, a3, wx), wy);
     const float c1 = lerp(lerp(b0, b1, wx), lerp(b2, b3, wx), wy);
-    return lerp(c0, c1, wz);
+    return live ? lerp(c0, c1, wz) : 0.0f;
   }
 };
 
@@ -160,7 +209,9 @@ struct BaseSampler<DT, LAYOUT_OCT> {
     split_coord(fx, v.nx, wx, kx);
     split_coord(fy, v.ny, wy, ky);
     split_coord(fz, v.nz, wz, kz);
-    const int e = __umul24(min(kz, v.nz - 1) + 1, v.plane) + packed_xy(v, kx, ky);
+    const bool live = occupied(v, kx, ky, kz);
+    CLOUD_SKIP_DEAD(live);
+    const int e = live ? __umul24(min(kz, v.nz - 1) + 1, v.plane) + packed_xy(v, kx, ky) : 0;
     float a0, a1, a2, a3, b0, b1, b2, b3;
     if constexpr (DT == DT_F32) {
       const float4* q = static_cast<const float4*>(v.base) + 2 * (size_t)e;
@@ -176,7 +227,7 @@ struct BaseSampler<DT, LAYOUT_OCT> {
     }
     const float c0 = lerp(lerp(a0, a1, wx), lerp(a2, a3, wx), wy);
     const float c1 = lerp(lerp(b0, b1, wx), lerp(b2, b3, wx), wy);
-    return lerp(c0, c1, wz);
+    return live ? lerp(c0, c1, wz) : 0.0f;
   }
 };
 

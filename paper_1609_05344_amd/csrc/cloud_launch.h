@@ -29,6 +29,11 @@ hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParam
 hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,
                        void* dst, hipStream_t s);
 
+// Build the occupancy bitmap (nbx * nby * nbz bricks of 2^lg texels) of a
+// dense volume of 2- or 4-byte texels into out.
+hipError_t launch_occupancy(const void* src, int elem_bytes, int nx, int ny, int nz, int lg,
+                            int nbx, int nby, int nbz, uint32_t* out, hipStream_t s);
+
 // Jitter offsets (as integers j * 2^24) of n pixels.
 hipError_t launch_jitter(const uint32_t* pxy, long long n, uint32_t frame, uint32_t seed,
                          uint32_t* out, hipStream_t s);

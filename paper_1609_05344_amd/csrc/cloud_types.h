@@ -29,7 +29,12 @@ struct DevVolume {
   float dsx, dsy, dsz, dox, doy, doz;
   float detail_weight;
   float bmin[3], bmax[3];
+  // occupancy bitmap (nullptr = none): bricks of 2^occ_lg texels per axis
+  const uint32_t* occ;
+  int occ_lg, occ_nbx, occ_nby, occ_words;
 };
+
+constexpr int kOccupancyWords = 1024;   // LDS budget of the bitmap (32768 bricks)
 
 struct DevParams {
   int steps, light_steps;

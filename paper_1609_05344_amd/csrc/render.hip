@@ -35,6 +35,7 @@ __global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams pr
   const int px = tx * 16 + (wave & 1) * 8 + (lane & 7);
   const int py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
   const bool inside = px < W && py < H;
+  stage_occupancy(vol);
   if (!COUNT && !inside) return;
 
   RayResult r = {0.0f, 0.0f, 0.0f, 0.0f, 0u};
@@ -60,6 +61,7 @@ __global__ __launch_bounds__(256) void rays_kernel(DevVolume vol, DevParams prm,
                                                    const uint32_t* __restrict__ pixel_xy,
                                                    long long n, float4* __restrict__ out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  stage_occupancy(vol);
   if (i >= n) return;
   const float ox = origins[3 * i], oy = origins[3 * i + 1], oz = origins[3 * i + 2];
   float dx = dirs[3 * i], dy = dirs[3 * i + 1], dz = dirs[3 * i + 2];
@@ -103,6 +105,39 @@ __global__ __launch_bounds__(256) void pack_kernel(const E* __restrict__ src, in
     o[6] = src[pb + (size_t)yb * nx + xa];
     o[7] = src[pb + (size_t)yb * nx + xb];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Occupancy bitmap: bit b is set when brick b -- texels [k, k + 2^lg] per
+// axis (one texel past the brick, so every footprint whose corner lies in the
+// brick is covered), clamped to the volume -- holds a non-zero texel.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t* __restrict__ out, int words) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) out[i] = 0u;
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void occupancy_kernel(const E* __restrict__ src, int nx, int ny,
+                                                        int nz, int lg, int nbx, int nby, int nbz,
+                                                        E magnitude_mask,
+                                                        uint32_t* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbx * nby * nbz) return;
+  const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+  const int x0 = bx << lg, y0 = by << lg, z0 = bz << lg;
+  const int x1 = min(x0 + (1 << lg), nx - 1), y1 = min(y0 + (1 << lg), ny - 1),
+            z1 = min(z0 + (1 << lg), nz - 1);
+  bool any = false;
+  for (int z = z0; z <= z1 && !any; ++z)
+    for (int y = y0; y <= y1 && !any; ++y)
+      for (int x = x0; x <= x1; ++x)
+        if (src[((size_t)z * ny + y) * nx + x] & magnitude_mask) {
+          any = true;
+          break;
+        }
+  if (any) atomicOr(&out[b >> 5], 1u << (b & 31));
 }
 
 // ---------------------------------------------------------------------------
@@ -264,6 +299,24 @@ hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, 
       hipLaunchKernelGGL((pack_kernel<uint16_t, 4>), dim3(blocks), dim3(256), 0, s,
                          static_cast<const uint16_t*>(src), nx, ny, nz, ez, static_cast<uint16_t*>(dst));
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_occupancy(const void* src, int elem_bytes, int nx, int ny, int nz, int lg,
+                            int nbx, int nby, int nbz, uint32_t* out, hipStream_t s) {
+  const int bricks = nbx * nby * nbz, words = (bricks + 31) / 32;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((words + 255) / 256), dim3(256), 0, s, out, words);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)((bricks + 255) / 256);
+  if (elem_bytes == 4)
+    hipLaunchKernelGGL((occupancy_kernel<uint32_t>), dim3(blocks), dim3(256), 0, s,
+                       static_cast<const uint32_t*>(src), nx, ny, nz, lg, nbx, nby, nbz,
+                       (uint32_t)0x7FFFFFFFu, out);
+  else
+    hipLaunchKernelGGL((occupancy_kernel<uint16_t>), dim3(blocks), dim3(256), 0, s,
+                       static_cast<const uint16_t*>(src), nx, ny, nz, lg, nbx, nby, nbz,
+                       (uint16_t)0x7FFFu, out);
   return hipGetLastError();
 }
 

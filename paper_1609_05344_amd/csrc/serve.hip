@@ -41,6 +41,7 @@ __device__ __forceinline__ int find_item(const ServeTable* tab, int n_items, int
 template <int DT, int LAYOUT, bool DETAIL>
 __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol, ServeTable* tab) {
   unsigned int* counters = tab->counters;
+  stage_occupancy(vol);
   __shared__ int s_tile;
   const int total = tab->total_tiles, n_items = tab->n_items, S = tab->supertile;
   const int home = blockIdx.x & 7;

@@ -101,3 +101,75 @@ def test_lookup_count_matches_oracle(cf, name, npix):
     packed = cf.cloud_volume_pack(cf.device_volume(sc), "oct")
     got2 = int(to_np(cf.cloud_count_lookups(packed, w.camera(1), w.params, 1, W, H))[0])
     assert got2 == got
+
+
+# ---------------------------------------------------------------------------
+# occupancy bitmap: exact empty-space skipping
+# ---------------------------------------------------------------------------
+
+def occupancy_reference(base_f64, lg):
+    """Brick occupancy from the definition: a brick is occupied when any texel
+    of [k, k + 2^lg] (clamped) per axis, k its first texel, is non-zero."""
+    nz, ny, nx = base_f64.shape
+    B = 1 << lg
+    nb = [((n - 1) >> lg) + 1 for n in (nx, ny, nz)]
+    bits = np.zeros(nb[0] * nb[1] * nb[2], dtype=bool)
+    for bz in range(nb[2]):
+        for by in range(nb[1]):
+            for bx in range(nb[0]):
+                blk = base_f64[bz * B:min(bz * B + B, nz - 1) + 1, by * B:min(by * B + B, ny - 1) + 1,
+                               bx * B:min(bx * B + B, nx - 1) + 1]
+                bits[(bz * nb[1] + by) * nb[0] + bx] = bool(np.any(blk != 0))
+    return bits
+
+
+@pytest.mark.parametrize("name,dtype", [("C1", "f32"), ("C3", "f16")])
+def test_occupancy_bitmap_matches_definition(cf, name, dtype):
+    say(f"occupancy bitmap {name} {dtype}")
+    w = scenes.workload(name)
+    sc = scenes.make_scene(w, dtype=dtype)
+    vol = cf.cloud_volume_occupancy(cf.device_volume(sc))
+    lg = vol.struct.occupancy_log2
+    words = to_np(vol.occupancy).view(np.uint32)
+    got = ((words[:, None] >> np.arange(32)[None, :]) & 1).reshape(-1).astype(bool)
+    want = occupancy_reference(sc.base_f64, lg)
+    assert np.array_equal(got[:want.size], want)
+    assert not got[want.size:].any()
+    assert 0 < want.mean() < 1
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("layout", ["dense", "quad", "oct"])
+def test_occupancy_skipping_is_exact(cf, dtype, layout):
+    w = scenes.workload("H")
+    say(f"occupancy skip {layout} {dtype}: H frame bitwise vs no skipping")
+    sc = scenes.make_scene(w, dtype=dtype)
+    plain = cf.device_volume(sc, layout=layout)
+    skip = cf.device_volume(sc, layout=layout, occupancy=True)
+    assert skip.struct.occupancy
+    a = to_np(cf.cloud_render(plain, w.camera(7), w.params, 7, w.width, w.height))
+    b = to_np(cf.cloud_render(skip, w.camera(7), w.params, 7, w.width, w.height))
+    assert np.array_equal(a, b)
+    na = int(to_np(cf.cloud_count_lookups(plain, w.camera(7), w.params, 7, 320, 180))[0])
+    nb = int(to_np(cf.cloud_count_lookups(skip, w.camera(7), w.params, 7, 320, 180))[0])
+    assert na == nb          # the method's lookups are the same; only fetches are skipped
+
+
+def test_occupancy_with_detail_and_odd_volume(cf):
+    say("occupancy skip: C3 with detail, and an odd-sized sparse volume vs oracle")
+    w = scenes.workload("C3")
+    sc = scenes.make_scene(w)
+    plain, skip = cf.device_volume(sc), cf.device_volume(sc, layout="oct", occupancy=True)
+    a = to_np(cf.cloud_render(plain, w.camera(0), w.params, 0, 480, 270))
+    b = to_np(cf.cloud_render(skip, w.camera(0), w.params, 0, 480, 270))
+    assert np.array_equal(a, b)
+    rng = np.random.default_rng(11)
+    base = np.where(rng.uniform(size=(21, 13, 35)) > 0.93, rng.uniform(size=(21, 13, 35)), 0.0)
+    st = scenes.quantise(base, "f32")
+    sc2 = scenes.Scene(scenes.workload("C1"), st, scenes.decode(st, "f32"))
+    cam = scenes.orbit_camera(1.3, 230.0, 25.0)
+    p = scenes.workload("C1", jitter=1).params
+    for layout in ("dense", "quad", "oct"):
+        v = cf.device_volume(sc2, layout=layout, occupancy=True)
+        got = to_np(cf.cloud_render(v, cam, p, 3, 48, 40))
+        assert max_err(got, O.render(oracle_volume(sc2), cam, p, 48, 40, frame=3)) < FP32_TOL

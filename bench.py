@@ -42,7 +42,8 @@ def _oracle_band(args):
     from paper_1609_05344_amd import scenes
     w = scenes.workload(name)
     sc = scenes.make_scene(w, dtype=dtype)
-    vol = O.OracleVolume(base=sc.base_f64)
+    vol = O.OracleVolume(base=sc.base_f64, detail=sc.detail_f64,
+                         detail_weight=w.params.detail_weight, detail_tiling=w.params.detail_tiling)
     ys, xs = np.meshgrid(np.arange(y0, y1), np.arange(w.width), indexing="ij")
     pix = np.stack([xs.reshape(-1), ys.reshape(-1)], 1)
     t = time.perf_counter()
@@ -89,10 +90,15 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
     outs = [torch.empty((H, W, 4), device="cuda") for _ in range(n_streams)]
     frame = [0] * n_streams
     lat, done_t = [], []
+
+    def orbit(s, f):
+        # the same stretch of the orbit (frames 10..69) that the plain leg times
+        return 10 + (s + f) % 60
+
     with cf.Server(vol, budget_bytes=n_streams * W * H * 40, max_batch=64) as srv:
         t_start = time.monotonic()
         for s in range(n_streams):
-            srv.submit(s, w.camera(0, view=s % 8), w.params, W, H, 0, outs[s])
+            srv.submit(s, w.camera(orbit(s, 0)), w.params, W, H, 0, outs[s])
         t_end = t_start + warm_s + seconds
         while time.monotonic() < t_end:
             got = srv.poll(256)
@@ -106,7 +112,7 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
                     lat.append((c["t_done_ns"] - c["t_submit_ns"]) * 1e-6)
                     done_t.append(c["t_done_ns"] * 1e-9)
                 frame[s] += 1
-                srv.submit(s, w.camera(frame[s], view=s % 8), w.params, W, H, frame[s], outs[s])
+                srv.submit(s, w.camera(orbit(s, frame[s])), w.params, W, H, frame[s], outs[s])
         st = srv.stats()
     done_t.sort()
     span = done_t[-1] - done_t[0] if len(done_t) > 1 else float("nan")
@@ -265,21 +271,27 @@ def main():
     # executed lookups per frame (library counter, outside the timed region)
     counts = torch.zeros((total,), dtype=torch.int64, device=dev)
     for f in range(total):
-        cf.cloud_count_lookups(vol, w.camera(f), p, f, W, H, out=counts[f:f + 1])
+        for v in range(w.views):
+            cf.cloud_count_lookups(vol, w.camera(f, view=v), p, f, W, H, out=counts[f:f + 1])
     counts = counts.cpu().numpy()
 
-    cur = torch.empty((H, W, 4), device=dev)
-    hist = torch.zeros((H, W, 4), device=dev)
+    V = w.views
+    cur = torch.empty((V, H, W, 4), device=dev)
+    hist = torch.zeros((V, H, W, 4), device=dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
 
     def frame(f, events=None):
         if events:
             events[0].record()
-        cf.cloud_render(vol, w.camera(f), p, f, W, H, out=cur)
+        if V == 1:
+            cf.cloud_render(vol, w.camera(f), p, f, W, H, out=cur[0])
+        else:
+            cf.cloud_render_views(vol, [w.camera(f, view=v) for v in range(V)], p, f, W, H, out=cur)
         if events:
             events[1].record()
-        cf.cloud_taa_resolve(cur, hist, hist, w.taa_blend, f)
+        for v in range(V):
+            cf.cloud_taa_resolve(cur[v], hist[v], hist[v], w.taa_blend, f)
 
     for f in range(args.warmup):
         frame(f)
@@ -297,7 +309,7 @@ def main():
     value = lk_timed / wall / 1e9
 
     elem = 4 if args.dtype == "f32" else 2
-    bytes_per_lookup = 8 * elem
+    bytes_per_lookup = 8 * elem * (2 if w.detail_n else 1)   # base (+ detail) footprint
     achieved = lk_frame * bytes_per_lookup / (render_ms * 1e-3) / 1e9
     line = {
         "metric": "Gsamples/s @1080p 8-step+TAA (executed trilinear density lookups per second; "

@@ -79,7 +79,10 @@ enum { CLOUD_F32 = 0, CLOUD_F16 = 1, CLOUD_BF16 = 2 };
  *          clamp((b - detail_weight*d) / (1 - detail_weight*d), 0, 1).
  *  layout  CLOUD_LAYOUT_* of base (a packed base is 16-byte aligned and
  *          normally made by cloud_volume_pack); nx, ny, nz always count
- *          texels. The detail volume is always dense.
+ *          texels. In a packed volume the detail, if any, is packed too:
+ *          [dnz][dny][dnx] entries of 8 texels, entry (z, y, x) holding the
+ *          texels at x|x+1, y|y+1, z|z+1 (each wrapped) in the OCT order,
+ *          16-byte aligned (cloud_volume_pack writes it after the base).
  *  occupancy       device, optional (NULL = none): a bitmap made by
  *          cloud_volume_occupancy, one bit per brick of 2^occupancy_log2
  *          texels per axis, clear when every texel a trilinear footprint

@@ -140,10 +140,17 @@ int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
       return fail(CLOUD_E_INVALID, "detail_tiling must be > 0");
     if ((long long)v->dnx * v->dny >= (1LL << 24))
       return fail(CLOUD_E_INVALID, "detail planes must hold < 2^24 texels");
-    rc = check_span(v->detail, (size_t)dt * dtype_size(v->ddtype), "volume detail");
+    // a packed volume keeps its detail in the oct-wrap form (8 texels per texel)
+    const bool packed = v->layout != CLOUD_LAYOUT_DENSE;
+    if (packed && reinterpret_cast<uintptr_t>(v->detail) % 16)
+      return fail(CLOUD_E_INVALID, "a packed detail volume must be 16-byte aligned");
+    rc = check_span(v->detail, (size_t)dt * dtype_size(v->ddtype) * (packed ? 8 : 1),
+                    "volume detail");
     if (rc) return rc;
     d.detail = v->detail;
     d.dnx = v->dnx; d.dny = v->dny; d.dnz = v->dnz;
+    auto pow2 = [](int n) { return (n & (n - 1)) == 0; };
+    d.dpow2 = pow2(v->dnx) && pow2(v->dny) && pow2(v->dnz);
     const int dn[3] = {v->dnx, v->dny, v->dnz};
     float* ds[3] = {&d.dsx, &d.dsy, &d.dsz};
     float* dof[3] = {&d.dox, &d.doy, &d.doz};
@@ -335,14 +342,28 @@ int cloud_count_lookups(const cloud_volume* volume, const cloud_camera* camera,
   CLOUD_GUARD_END
 }
 
+// Bytes of a packed copy: the base in `layout`, then (256-byte aligned) the
+// detail in its oct-wrap form, if the volume has one.
+static int packed_bytes(const cloud_volume* dense, int layout, size_t* base_bytes, size_t* total) {
+  int rc = volume_layout_bytes(dense, layout, base_bytes);
+  if (rc) return rc;
+  *total = *base_bytes;
+  if (dense->detail) {
+    const size_t dt = (size_t)dense->dnx * dense->dny * dense->dnz;
+    *total = ((*base_bytes + 255) & ~(size_t)255) + dt * 8 * dtype_size(dense->dtype);
+  }
+  return CLOUD_OK;
+}
+
 int cloud_volume_packed_bytes(const cloud_volume* dense, int32_t layout, uint64_t* bytes) {
   CLOUD_GUARD_BEGIN
   clear_error();
   if (!bytes) return fail(CLOUD_E_INVALID, "bytes is NULL");
-  size_t b = 0;
-  const int rc = volume_layout_bytes(dense, layout, &b);
+  if (!dense) return fail(CLOUD_E_INVALID, "volume is NULL");
+  size_t b = 0, total = 0;
+  const int rc = packed_bytes(dense, layout, &b, &total);
   if (rc) return rc;
-  *bytes = b;
+  *bytes = layout == CLOUD_LAYOUT_DENSE ? b : total;
   return CLOUD_OK;
   CLOUD_GUARD_END
 }
@@ -359,21 +380,34 @@ int cloud_volume_pack(const cloud_volume* dense, int32_t layout, void* dst, uint
   DevVolume v;
   int dtype, rc;
   if ((rc = prepare_volume(dense, &v, &dtype))) return rc;
-  size_t need = 0;
-  if ((rc = volume_layout_bytes(dense, layout, &need))) return rc;
+  size_t base_bytes = 0, need = 0;
+  if ((rc = packed_bytes(dense, layout, &base_bytes, &need))) return rc;
   if (dst_bytes < need) return fail(CLOUD_E_INVALID, "dst is smaller than the packed volume");
   if (reinterpret_cast<uintptr_t>(dst) % 16) return fail(CLOUD_E_INVALID, "dst must be 16-byte aligned");
   if ((rc = check_span(dst, need, "dst"))) return rc;
   const char* d0 = static_cast<const char*>(dst);
+  const size_t es = dtype_size(dtype);
   const char* s0 = static_cast<const char*>(dense->base);
-  const size_t sbytes = (size_t)dense->nx * dense->ny * dense->nz * dtype_size(dtype);
+  const size_t sbytes = (size_t)dense->nx * dense->ny * dense->nz * es;
   if (d0 < s0 + sbytes && s0 < d0 + need) return fail(CLOUD_E_INVALID, "dst overlaps the volume");
-  hipError_t e = launch_pack(dense->base, (int)dtype_size(dtype), dense->nx, dense->ny, dense->nz,
-                             layout, dst, static_cast<hipStream_t>(hip_stream));
+  if (dense->detail) {
+    const char* t0 = static_cast<const char*>(dense->detail);
+    const size_t tbytes = (size_t)dense->dnx * dense->dny * dense->dnz * es;
+    if (d0 < t0 + tbytes && t0 < d0 + need) return fail(CLOUD_E_INVALID, "dst overlaps the detail volume");
+  }
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = launch_pack(dense->base, (int)es, dense->nx, dense->ny, dense->nz, layout, dst, s);
   if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("pack launch: ") + hipGetErrorString(e));
+  void* ddst = nullptr;
+  if (dense->detail) {
+    ddst = static_cast<char*>(dst) + ((base_bytes + 255) & ~(size_t)255);
+    e = launch_pack_detail(dense->detail, (int)es, dense->dnx, dense->dny, dense->dnz, ddst, s);
+    if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("pack launch: ") + hipGetErrorString(e));
+  }
   *packed = *dense;
   packed->base = dst;
   packed->layout = layout;
+  if (dense->detail) packed->detail = ddst;
   return CLOUD_OK;
   CLOUD_GUARD_END
 }

@@ -261,9 +261,51 @@ __device__ __forceinline__ float trilerp_repeat(const void* __restrict__ base, i
   return lerp(lerp(c00, c10, wy), lerp(c01, c11, wy), wz);
 }
 
+// Repeat-addressed lookup in the packed detail volume: entry (z, y, x) of
+// [dnz][dny][dnx] x 8 holds the texels (x|x+1, y|y+1, z|z+1) mod n in the
+// order of the oct layout, so a lookup is one aligned fetch (two for float32).
+// Same lerps, in the same order, as trilerp_repeat.
+template <int DT>
+__device__ __forceinline__ float detail_oct(const DevVolume& v, float fx, float fy, float fz) {
+  const float lim = 1048576.0f;
+  fx = fminf(fmaxf(fx, -lim), lim);
+  fy = fminf(fmaxf(fy, -lim), lim);
+  fz = fminf(fmaxf(fz, -lim), lim);
+  const float x0f = floorf(fx), y0f = floorf(fy), z0f = floorf(fz);
+  const float wx = fx - x0f, wy = fy - y0f, wz = fz - z0f;
+  int xa, ya, za;
+  if (v.dpow2) {
+    xa = (int)x0f & (v.dnx - 1);
+    ya = (int)y0f & (v.dny - 1);
+    za = (int)z0f & (v.dnz - 1);
+  } else {
+    xa = wrap_index((int)x0f, v.dnx);
+    ya = wrap_index((int)y0f, v.dny);
+    za = wrap_index((int)z0f, v.dnz);
+  }
+  const int e = (za * v.dny + ya) * v.dnx + xa;
+  float a0, a1, a2, a3, b0, b1, b2, b3;
+  if constexpr (DT == DT_F32) {
+    const float4* q = static_cast<const float4*>(v.detail) + 2 * (size_t)e;
+    const float4 A = q[0], B = q[1];
+    a0 = A.x; a1 = A.y; a2 = A.z; a3 = A.w;
+    b0 = B.x; b1 = B.y; b2 = B.z; b3 = B.w;
+  } else {
+    const uint4 Q = static_cast<const uint4*>(v.detail)[e];
+    unpack2<DT>(Q.x, a0, a1);
+    unpack2<DT>(Q.y, a2, a3);
+    unpack2<DT>(Q.z, b0, b1);
+    unpack2<DT>(Q.w, b2, b3);
+  }
+  const float c00 = lerp(a0, a1, wx), c10 = lerp(a2, a3, wx);
+  const float c01 = lerp(b0, b1, wx), c11 = lerp(b2, b3, wx);
+  return lerp(lerp(c00, c10, wy), lerp(c01, c11, wy), wz);
+}
+
 // Density at world point p (Section 1). With a detail volume the base shape
 // is eroded: clamp((b - w d) / (1 - w d), 0, 1); where b <= 0 the result is 0
-// whatever d is, so the detail lookup is skipped there.
+// whatever d is, so the detail lookup is skipped there. A packed volume keeps
+// its detail packed too.
 template <int DT, int LAYOUT, bool DETAIL>
 __device__ __forceinline__ float density(const DevVolume& v, float px, float py, float pz) {
   const float b = BaseSampler<DT, LAYOUT>::fetch(v, fmaf(px, v.sx, v.ox), fmaf(py, v.sy, v.oy),
@@ -272,8 +314,11 @@ __device__ __forceinline__ float density(const DevVolume& v, float px, float py,
     return b;
   } else {
     if (!(b > 0.0f)) return 0.0f;
-    const float d = trilerp_repeat<DT>(v.detail, v.dnx, v.dny, v.dnz, fmaf(px, v.dsx, v.dox),
-                                       fmaf(py, v.dsy, v.doy), fmaf(pz, v.dsz, v.doz));
+    const float dx = fmaf(px, v.dsx, v.dox), dy = fmaf(py, v.dsy, v.doy),
+                dz = fmaf(pz, v.dsz, v.doz);
+    float d;
+    if constexpr (LAYOUT == LAYOUT_DENSE) d = trilerp_repeat<DT>(v.detail, v.dnx, v.dny, v.dnz, dx, dy, dz);
+    else d = detail_oct<DT>(v, dx, dy, dz);
     const float wd = v.detail_weight * d;
     return fminf(fmaxf((b - wd) / (1.0f - wd), 0.0f), 1.0f);
   }

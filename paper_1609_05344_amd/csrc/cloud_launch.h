@@ -29,6 +29,10 @@ hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParam
 hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,
                        void* dst, hipStream_t s);
 
+// Pack a dense repeat-addressed detail volume into its oct-wrap layout.
+hipError_t launch_pack_detail(const void* src, int elem_bytes, int nx, int ny, int nz, void* dst,
+                              hipStream_t s);
+
 // Build the occupancy bitmap (nbx * nby * nbz bricks of 2^lg texels) of a
 // dense volume of 2- or 4-byte texels into out.
 hipError_t launch_occupancy(const void* src, int elem_bytes, int nx, int ny, int nz, int lg,

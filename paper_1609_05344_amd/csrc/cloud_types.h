@@ -24,8 +24,9 @@ struct DevVolume {
   // continuous texel coordinate along each axis: f = p * s + o, texel k's
   // centre at f = k (texel centres at box_min + (k + 0.5) * extent / n)
   float sx, sy, sz, ox, oy, oz;
-  const void* detail;
+  const void* detail;           // dense, or oct-wrap packed when the base is packed
   int dnx, dny, dnz;
+  int dpow2;                    // every detail dim is a power of two
   float dsx, dsy, dsz, dox, doy, doz;
   float detail_weight;
   float bmin[3], bmax[3];

@@ -107,6 +107,27 @@ __global__ __launch_bounds__(256) void pack_kernel(const E* __restrict__ src, in
   }
 }
 
+// Detail packing (repeat addressing): entry (z, y, x) holds the texels at
+// x|x+1, y|y+1, z|z+1, each wrapped, in the oct order.
+template <typename E>
+__global__ __launch_bounds__(256) void pack_wrap_kernel(const E* __restrict__ src, int nx, int ny,
+                                                        int nz, E* __restrict__ dst) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nx * ny * nz) return;
+  const int x = (int)(e % nx), y = (int)((e / nx) % ny), z = (int)(e / ((long long)nx * ny));
+  const int x1 = x + 1 == nx ? 0 : x + 1, y1 = y + 1 == ny ? 0 : y + 1, z1 = z + 1 == nz ? 0 : z + 1;
+  const size_t p0 = (size_t)z * ny * nx, p1 = (size_t)z1 * ny * nx;
+  E* o = dst + (size_t)e * 8;
+  o[0] = src[p0 + (size_t)y * nx + x];
+  o[1] = src[p0 + (size_t)y * nx + x1];
+  o[2] = src[p0 + (size_t)y1 * nx + x];
+  o[3] = src[p0 + (size_t)y1 * nx + x1];
+  o[4] = src[p1 + (size_t)y * nx + x];
+  o[5] = src[p1 + (size_t)y * nx + x1];
+  o[6] = src[p1 + (size_t)y1 * nx + x];
+  o[7] = src[p1 + (size_t)y1 * nx + x1];
+}
+
 // ---------------------------------------------------------------------------
 // Occupancy bitmap: bit b is set when brick b -- texels [k, k + 2^lg] per
 // axis (one texel past the brick, so every footprint whose corner lies in the
@@ -299,6 +320,19 @@ hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, 
       hipLaunchKernelGGL((pack_kernel<uint16_t, 4>), dim3(blocks), dim3(256), 0, s,
                          static_cast<const uint16_t*>(src), nx, ny, nz, ez, static_cast<uint16_t*>(dst));
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_detail(const void* src, int elem_bytes, int nx, int ny, int nz, void* dst,
+                              hipStream_t s) {
+  const long long n = (long long)nx * ny * nz;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (elem_bytes == 4)
+    hipLaunchKernelGGL((pack_wrap_kernel<uint32_t>), dim3(blocks), dim3(256), 0, s,
+                       static_cast<const uint32_t*>(src), nx, ny, nz, static_cast<uint32_t*>(dst));
+  else
+    hipLaunchKernelGGL((pack_wrap_kernel<uint16_t>), dim3(blocks), dim3(256), 0, s,
+                       static_cast<const uint16_t*>(src), nx, ny, nz, static_cast<uint16_t*>(dst));
   return hipGetLastError();
 }
 

@@ -173,3 +173,21 @@ def test_occupancy_with_detail_and_odd_volume(cf):
         v = cf.device_volume(sc2, layout=layout, occupancy=True)
         got = to_np(cf.cloud_render(v, cam, p, 3, 48, 40))
         assert max_err(got, O.render(oracle_volume(sc2), cam, p, 48, 40, frame=3)) < FP32_TOL
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_packed_detail_matches_dense_and_oracle(cf, dtype):
+    say(f"packed detail {dtype}: non-power-of-two detail dims, quad and oct, vs dense and oracle")
+    rng = np.random.default_rng(21)
+    base = np.clip(rng.uniform(-0.2, 1.0, size=(18, 12, 20)), 0, 1)
+    det = rng.uniform(0, 1, size=(6, 5, 7))
+    w = scenes.workload("C3")
+    bs, ds = scenes.quantise(base, dtype), scenes.quantise(det, dtype)
+    sc = scenes.Scene(w, bs, scenes.decode(bs, dtype), ds, scenes.decode(ds, dtype))
+    cam = scenes.orbit_camera(1.4, 215.0, 18.0)
+    dense = to_np(cf.cloud_render(cf.device_volume(sc), cam, w.params, 2, 64, 48))
+    for layout in ("quad", "oct"):
+        v = cf.device_volume(sc, layout=layout, occupancy=True)
+        assert np.array_equal(to_np(cf.cloud_render(v, cam, w.params, 2, 64, 48)), dense)
+    tol = FP32_TOL if dtype == "f32" else HALF_TOL
+    assert max_err(dense, O.render(oracle_volume(sc), cam, w.params, 64, 48, frame=2)) < tol

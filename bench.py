@@ -29,6 +29,32 @@ sys.path.insert(0, ROOT)
 
 MI355X_HBM_GBPS = 8000.0
 MI355X_FP32_VECTOR_TFLOPS = 157.3
+KERNEL_SOURCES = ["cloud_device.h", "cloud_types.h", "render.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
+
+
+def kernel_source_sha1() -> str:
+    """Hash of the sources the render kernel is built from: a recorded counter
+    measurement applies only while this hash is unchanged."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1609_05344_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(config: dict):
+    """HBM bytes per render launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE measurement, or None when the kernel or config differ."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha1") != kernel_source_sha1() or rec.get("config") != config:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 # ---------------------------------------------------------------------------
@@ -79,7 +105,7 @@ def cpu_baseline(name: str, dtype: str, frames: int, cores: int) -> dict:
 # ---------------------------------------------------------------------------
 
 def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams: int,
-                       seconds: float, warm_s: float = 0.5) -> dict:
+                       seconds: float, warm_s: float = 0.5, queues: int = 1) -> dict:
     """n_streams streams of the workload, each submitting its next frame as
     soon as the previous one completes; frames/s and frame latency
     (submit -> done) over the measured window."""
@@ -95,7 +121,7 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
         # the same stretch of the orbit (frames 10..69) that the plain leg times
         return 10 + (s + f) % 60
 
-    with cf.Server(vol, budget_bytes=n_streams * W * H * 40, max_batch=64) as srv:
+    with cf.Server(vol, budget_bytes=n_streams * W * H * 40, max_batch=64, queues=queues) as srv:
         t_start = time.monotonic()
         for s in range(n_streams):
             srv.submit(s, w.camera(orbit(s, 0)), w.params, W, H, 0, outs[s])
@@ -121,12 +147,12 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
             "frames_per_s": round(fps, 1), "ms_per_frame": round(1e3 / fps, 4) if fps else None,
             "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
             "latency_p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "frames": len(lat), "batches": st["batches"]}
+            "frames": len(lat), "batches": st["batches"], "queues": queues}
 
 
 def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: float = 1.0,
                    n_streams: int = 64, seed: int = 5344, ring: int = 4,
-                   budget_bytes: int = 64 << 30) -> dict:
+                   budget_bytes: int = 64 << 30, queues: int = 1) -> dict:
     """Open-loop serving load: n_streams camera streams, each with a
     resolution from {640x360, 1280x720, 1920x1080, 3840x2160} and a step
     count from {8, 16, 32, 128} drawn once; Poisson arrivals at rate_hz in
@@ -149,7 +175,8 @@ def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: fl
     busy = nobuf = 0
     gaps = rng.exponential(1.0 / rate_hz, size=int(rate_hz * (warm_s + seconds) * 1.5) + 16)
     which = rng.integers(n_streams, size=gaps.size)
-    with cf.Server(vol, budget_bytes=budget_bytes, max_batch=64, max_queue=4096) as srv:
+    with cf.Server(vol, budget_bytes=budget_bytes, max_batch=64, max_queue=4096,
+                   queues=queues) as srv:
         t0 = time.monotonic()
         t_arr = t0 + np.cumsum(gaps)
         k, t_end = 0, t0 + warm_s + seconds
@@ -193,6 +220,68 @@ def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: fl
             "batches": st["batches"], "streams": n_streams}
 
 
+def quality_report(cf, scenes, torch) -> dict:
+    """Reported numbers (the gates live in the tests):
+    * precision forms at C3 (1080p, 128^3 base + 32^3 detail, 16 jittered
+      steps): max and p99 abs RGBA error over 20000 seeded pixels of the FP32,
+      FP16 and BF16 storage paths against the FP64 oracle on the decoded stored
+      volume, and of the 16-bit paths against the oracle on the FP32 volume;
+    * 8 jittered steps + TAA against the 128-step unjittered render (C2, 720p):
+      the same camera after a 16-frame accumulation at a fixed camera, next to
+      one 8-step frame with and without jitter."""
+    import numpy as np
+    from oracle import cloud as O
+    out = {}
+    w = scenes.workload("C3")
+    pix = scenes.random_pixels(w.width, w.height, 20000, seed=99)
+    src32 = scenes.make_scene(w, dtype="f32")
+
+    def ovol(sc):
+        return O.OracleVolume(base=sc.base_f64, detail=sc.detail_f64,
+                              detail_weight=w.params.detail_weight,
+                              detail_tiling=w.params.detail_tiling)
+
+    ref32 = O.render(ovol(src32), w.camera(0), w.params, w.width, w.height, frame=0, pixels=pix)
+    prec = {}
+    for dt in ("f32", "f16", "bf16"):
+        sc = scenes.make_scene(w, dtype=dt)
+        vol = cf.device_volume(sc, layout="oct")
+        img = cf.cloud_render(vol, w.camera(0), w.params, 0, w.width, w.height).cpu().numpy()
+        got = img[pix[:, 1], pix[:, 0]].astype(np.float64)
+        ref = ref32 if dt == "f32" else O.render(ovol(sc), w.camera(0), w.params, w.width,
+                                                  w.height, frame=0, pixels=pix)
+        e_dec, e_src = np.abs(got - ref), np.abs(got - ref32)
+        prec[dt] = {"max_vs_oracle_on_stored": float(e_dec.max()),
+                    "p99_vs_oracle_on_stored": float(np.percentile(e_dec, 99)),
+                    "max_vs_oracle_on_f32_source": float(e_src.max()),
+                    "p99_vs_oracle_on_f32_source": float(np.percentile(e_src, 99))}
+    out["precision_C3"] = prec
+
+    w2 = scenes.workload("C2")
+    vol = cf.device_volume(scenes.make_scene(w2), layout="quad", occupancy=True)
+    W, H = w2.width, w2.height
+    cam = w2.camera(0)
+    from dataclasses import replace
+    ref = cf.cloud_render(vol, cam, replace(w2.params, steps=128, jitter=0), 0, W, H).cpu().numpy()
+    hist = torch.zeros((H, W, 4), device="cuda")
+    cur = torch.empty((H, W, 4), device="cuda")
+    for f in range(16):
+        cf.cloud_render(vol, cam, w2.params, f, W, H, out=cur)
+        cf.cloud_taa_resolve(cur, hist, hist, w2.taa_blend, f)
+    taa = hist.cpu().numpy()
+    one = cf.cloud_render(vol, cam, w2.params, 15, W, H).cpu().numpy()
+    flat = cf.cloud_render(vol, cam, replace(w2.params, jitter=0), 15, W, H).cpu().numpy()
+
+    def err(a):
+        d = np.abs(a.astype(np.float64) - ref)
+        return {"mean_abs": float(d.mean()), "p99_abs": float(np.percentile(d, 99)),
+                "max_abs": float(d.max())}
+
+    out["steps8_vs_128_C2"] = {"jitter_taa_16_frames": err(taa), "jitter_one_frame": err(one),
+                              "no_jitter": err(flat)}
+    return out
+
+
 # ---------------------------------------------------------------------------
 # GPU run
 # ---------------------------------------------------------------------------
@@ -210,12 +299,15 @@ def main():
     ap.add_argument("--served-dtype", default="f16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--served-layout", default="oct", choices=["dense", "quad", "oct"])
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--serve-queues", type=int, default=1, choices=[1, 2])
     ap.add_argument("--no-occupancy", action="store_true",
                     help="render without the exact empty-space-skipping bitmap")
     ap.add_argument("--serve-poisson", default="",
                     help="comma-separated total arrival rates (req/s): run only the open-loop "
                          "64-stream serving load at each rate and print one JSON line")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--quality", action="store_true",
+                    help="print the precision-form and step-count error report instead")
     ap.add_argument("--cpu-frames", type=int, default=36)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -228,11 +320,20 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.quality:
+        import torch
+        import paper_1609_05344_amd as cf
+        from paper_1609_05344_amd import scenes
+        print(json.dumps({"metric": "RGBA error report", "report": quality_report(cf, scenes, torch)}),
+              flush=True)
+        return
+
     if args.serve_poisson:
         import torch
         import paper_1609_05344_amd as cf
         from paper_1609_05344_amd import scenes
-        runs = [served_poisson(cf, scenes, torch, float(r), args.serve_seconds)
+        runs = [served_poisson(cf, scenes, torch, float(r), args.serve_seconds,
+                               queues=args.serve_queues)
                 for r in args.serve_poisson.split(",")]
         print(json.dumps({"metric": "served frame latency p50/p99, open-loop Poisson arrivals",
                           "unit": "ms", "config": {"workload": "64 streams, resolutions in "
@@ -311,6 +412,8 @@ def main():
     elem = 4 if args.dtype == "f32" else 2
     bytes_per_lookup = 8 * elem * (2 if w.detail_n else 1)   # base (+ detail) footprint
     achieved = lk_frame * bytes_per_lookup / (render_ms * 1e-3) / 1e9
+    traffic_key = {"workload": w.name, "dtype": args.dtype, "layout": args.layout,
+                   "occupancy": not args.no_occupancy}
     line = {
         "metric": "Gsamples/s @1080p 8-step+TAA (executed trilinear density lookups per second; "
                   "ms/frame in ms_per_step)",
@@ -334,16 +437,21 @@ def main():
                    "lookups_per_frame": round(lk_frame)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": MI355X_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / MI355X_HBM_GBPS, 4),
-                     "traffic": None, "kernel": "render_kernel",
+                     "traffic": recorded_traffic(traffic_key), "kernel": "render_kernel",
                      "kernel_ms": round(render_ms, 4),
-                     "bytes_per_lookup": bytes_per_lookup},
+                     "algorithmic_bytes_per_launch": round(lk_frame * bytes_per_lookup),
+                     "bytes_per_lookup": bytes_per_lookup,
+                     "traffic_note": "HBM bytes per launch: calibrated rocprofv3 FETCH_SIZE + "
+                                     "WRITE_SIZE recorded in profiles/render_traffic.json for "
+                                     "this kernel source and config (null if either changed)"},
         "cpu_baseline": cpu,
     }
     if not args.no_served:
         del cur, hist, vol
         torch.cuda.empty_cache()
         served = served_closed_loop(cf, scenes, torch, w, args.served_dtype, args.served_layout,
-                                    args.served_streams, args.served_seconds)
+                                    args.served_streams, args.served_seconds,
+                                    queues=args.serve_queues)
         served["plain_frames_per_s"] = round(1e3 / ms_per_step, 1)
         served["speedup_vs_plain"] = round(served["frames_per_s"] * ms_per_step / 1e3, 3)
         line["served"] = served

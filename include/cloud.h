@@ -239,7 +239,9 @@ int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t ds
 /* Launch-shape knob, process-wide, for tuning and benchmarking; results do
  * not depend on it. Keys: "supertile" (0..64, default 4) -- the render walks
  * its 16x16-pixel tiles in S x S super-tiles so that the tiles an XCD works on
- * together cover a compact patch of the image (0 = row-major). */
+ * together cover a compact patch of the image (0 = row-major); "taa_tile"
+ * (16, 32 or 64, default 16) -- the resolve's tile width in pixels (each
+ * tile holds 256 pixels). */
 int cloud_tune(const char* key, int32_t value);
 
 /* Checks that [ptr, ptr + bytes) lies inside one HIP device allocation: the
@@ -294,6 +296,9 @@ typedef struct {
   int32_t device;             /* HIP device ordinal */
   float taa_blend;            /* resolve blend, (0, 1] */
   int32_t use_graphs;         /* 1: replay captured graphs; 0: plain launches */
+  int32_t queues;             /* HIP streams batches alternate over: 1 (0 means
+                               * 1) keeps batches in order on one queue; 2 lets
+                               * a batch start while the previous one drains */
 } cloud_serve_config;
 
 typedef struct {

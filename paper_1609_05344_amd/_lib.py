@@ -318,7 +318,8 @@ def cloud_taa_resolve(current, history, out, blend: float, frame_index: int, str
 
 class cloud_serve_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", c_uint64), ("max_batch", c_int32), ("max_queue", c_int32),
-                ("device", c_int32), ("taa_blend", c_float), ("use_graphs", c_int32)]
+                ("device", c_int32), ("taa_blend", c_float), ("use_graphs", c_int32),
+                ("queues", c_int32)]
 
 
 class cloud_serve_stats_t(ctypes.Structure):
@@ -358,11 +359,11 @@ class Server:
 
     def __init__(self, volume: Volume, budget_bytes: int = 64 << 30, max_batch: int = 64,
                  max_queue: int = 1024, device: int = 0, taa_blend: float = 0.1,
-                 use_graphs: bool = True):
+                 use_graphs: bool = True, queues: int = 1):
         self.lib = _bind_serve(load())
         self.volume = volume
         cfg = cloud_serve_config(int(budget_bytes), int(max_batch), int(max_queue), int(device),
-                                 float(taa_blend), 1 if use_graphs else 0)
+                                 float(taa_blend), 1 if use_graphs else 0, int(queues))
         h = c_void_p()
         check(self.lib.cloud_serve_create(ctypes.byref(volume.struct), ctypes.byref(cfg),
                                           ctypes.byref(h)))

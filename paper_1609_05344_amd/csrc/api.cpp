@@ -532,6 +532,12 @@ int cloud_tune(const char* key, int32_t value) {
     tuning().supertile = value;
     return CLOUD_OK;
   }
+  if (k == "taa_tile") {
+    if (value != 16 && value != 32 && value != 64)
+      return fail(CLOUD_E_INVALID, "taa_tile must be 16, 32 or 64");
+    tuning().taa_tile = value;
+    return CLOUD_OK;
+  }
   return fail(CLOUD_E_INVALID, "unknown tuning key " + k);
   CLOUD_GUARD_END
 }

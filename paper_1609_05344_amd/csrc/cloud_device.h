@@ -306,26 +306,39 @@ __device__ __forceinline__ float detail_oct(const DevVolume& v, float fx, float 
 // is eroded: clamp((b - w d) / (1 - w d), 0, 1); where b <= 0 the result is 0
 // whatever d is, so the detail lookup is skipped there. A packed volume keeps
 // its detail packed too.
+// Density from continuous texel coordinates of the base (f) and, with a
+// detail volume, of the detail (g).
 template <int DT, int LAYOUT, bool DETAIL>
-__device__ __forceinline__ float density(const DevVolume& v, float px, float py, float pz) {
-  const float b = BaseSampler<DT, LAYOUT>::fetch(v, fmaf(px, v.sx, v.ox), fmaf(py, v.sy, v.oy),
-                                                 fmaf(pz, v.sz, v.oz));
+__device__ __forceinline__ float density_tex(const DevVolume& v, float fx, float fy, float fz,
+                                             float gx, float gy, float gz) {
+  const float b = BaseSampler<DT, LAYOUT>::fetch(v, fx, fy, fz);
   if constexpr (!DETAIL) {
     return b;
   } else {
     if (!(b > 0.0f)) return 0.0f;
-    const float dx = fmaf(px, v.dsx, v.dox), dy = fmaf(py, v.dsy, v.doy),
-                dz = fmaf(pz, v.dsz, v.doz);
     float d;
-    if constexpr (LAYOUT == LAYOUT_DENSE) d = trilerp_repeat<DT>(v.detail, v.dnx, v.dny, v.dnz, dx, dy, dz);
-    else d = detail_oct<DT>(v, dx, dy, dz);
+    if constexpr (LAYOUT == LAYOUT_DENSE) d = trilerp_repeat<DT>(v.detail, v.dnx, v.dny, v.dnz, gx, gy, gz);
+    else d = detail_oct<DT>(v, gx, gy, gz);
     const float wd = v.detail_weight * d;
     return fminf(fmaxf((b - wd) / (1.0f - wd), 0.0f), 1.0f);
   }
 }
 
+template <int DT, int LAYOUT, bool DETAIL>
+__device__ __forceinline__ float density(const DevVolume& v, float px, float py, float pz) {
+  if constexpr (DETAIL)
+    return density_tex<DT, LAYOUT, DETAIL>(v, fmaf(px, v.sx, v.ox), fmaf(py, v.sy, v.oy),
+                                           fmaf(pz, v.sz, v.oz), fmaf(px, v.dsx, v.dox),
+                                           fmaf(py, v.dsy, v.doy), fmaf(pz, v.dsz, v.doz));
+  else
+    return density_tex<DT, LAYOUT, DETAIL>(v, fmaf(px, v.sx, v.ox), fmaf(py, v.sy, v.oy),
+                                           fmaf(pz, v.sz, v.oz), 0.0f, 0.0f, 0.0f);
+}
+
 // Transmittance towards the sun from p (Section 1): L midpoint samples of
-// equal steps up to the box exit along s, Beer-Lambert over their sum.
+// equal steps up to the box exit along s, Beer-Lambert over their sum. The
+// sample points are stepped in texel coordinates directly (the map from world
+// to texel coordinates is affine).
 template <int DT, int LAYOUT, bool DETAIL>
 __device__ __forceinline__ float light_transmittance(const DevVolume& v, const DevParams& P,
                                                      float px, float py, float pz) {
@@ -335,11 +348,24 @@ __device__ __forceinline__ float light_transmittance(const DevVolume& v, const D
   if (P.s_axis[2]) tx = fminf(tx, (P.light_bound[2] - pz) * P.inv_s[2]);
   const float dl = tx * P.inv_light_steps;
   const float stx = dl * P.s[0], sty = dl * P.s[1], stz = dl * P.s[2];
+  const float fx0 = fmaf(px, v.sx, v.ox), fy0 = fmaf(py, v.sy, v.oy), fz0 = fmaf(pz, v.sz, v.oz);
+  const float dfx = stx * v.sx, dfy = sty * v.sy, dfz = stz * v.sz;
+  float gx0 = 0.0f, gy0 = 0.0f, gz0 = 0.0f, dgx = 0.0f, dgy = 0.0f, dgz = 0.0f;
+  if constexpr (DETAIL) {
+    gx0 = fmaf(px, v.dsx, v.dox);
+    gy0 = fmaf(py, v.dsy, v.doy);
+    gz0 = fmaf(pz, v.dsz, v.doz);
+    dgx = stx * v.dsx;
+    dgy = sty * v.dsy;
+    dgz = stz * v.dsz;
+  }
   float acc = 0.0f;
 #pragma unroll kLightUnroll
   for (int k = 0; k < P.light_steps; ++k) {
     const float h = (float)k + 0.5f;
-    acc += density<DT, LAYOUT, DETAIL>(v, fmaf(h, stx, px), fmaf(h, sty, py), fmaf(h, stz, pz));
+    acc += density_tex<DT, LAYOUT, DETAIL>(v, fmaf(h, dfx, fx0), fmaf(h, dfy, fy0),
+                                           fmaf(h, dfz, fz0), fmaf(h, dgx, gx0),
+                                           fmaf(h, dgy, gy0), fmaf(h, dgz, gz0));
   }
   return exp2f(-P.alpha_log2e * dl * acc);
 }

@@ -10,6 +10,7 @@ namespace cloud {
 // Launch-shape knobs (process-wide; set through cloud_tune).
 struct Tuning {
   int supertile = 4;   // render tile walk: S x S super-tiles (0 = row-major)
+  int taa_tile = 32;   // resolve tile width in pixels (16, 32 or 64; 256 pixels a tile)
 };
 Tuning& tuning();
 

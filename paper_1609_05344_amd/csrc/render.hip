@@ -20,8 +20,19 @@ Tuning& tuning() {
 // the image.
 // ---------------------------------------------------------------------------
 
+// Minimum waves per SIMD the register allocator must leave room for (0: the
+// compiler's choice).
+#ifndef CLOUD_RENDER_WAVES
+#define CLOUD_RENDER_WAVES 0
+#endif
+#if CLOUD_RENDER_WAVES > 0
+#define CLOUD_RENDER_ATTR __attribute__((amdgpu_waves_per_eu(CLOUD_RENDER_WAVES)))
+#else
+#define CLOUD_RENDER_ATTR
+#endif
+
 template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
-__global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams prm,
+__global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume vol, DevParams prm,
                                                      DevCameras cams, uint32_t frame, int W,
                                                      int H, int tiles_x, int tiles_y, int S,
                                                      float4* __restrict__ out,
@@ -161,49 +172,6 @@ __global__ __launch_bounds__(256) void occupancy_kernel(const E* __restrict__ sr
   if (any) atomicOr(&out[b >> 5], 1u << (b & 31));
 }
 
-// ---------------------------------------------------------------------------
-// Temporal resolve (Section 3.2): a 16x16 tile of the current frame plus a
-// one-pixel edge-clamped halo is staged in LDS, so each current pixel is read
-// from HBM once although nine threads use it.
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void taa_kernel(const float4* __restrict__ cur,
-                                                  const float4* hist, float4* out, int W, int H,
-                                                  int tiles_x, float blend) {
-  __shared__ float4 tile[18][18];
-  const int tyi = blockIdx.x / tiles_x, txi = blockIdx.x - tyi * tiles_x;
-  const int bx = txi * 16, by = tyi * 16;
-  for (int i = threadIdx.x; i < 18 * 18; i += 256) {
-    const int ly = i / 18, lx = i - ly * 18;
-    const int gx = min(max(bx + lx - 1, 0), W - 1);
-    const int gy = min(max(by + ly - 1, 0), H - 1);
-    tile[ly][lx] = cur[(size_t)gy * W + gx];
-  }
-  __syncthreads();
-  const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
-  const int px = bx + lx, py = by + ly;
-  if (px >= W || py >= H) return;
-  const float4 c = tile[ly + 1][lx + 1];
-  float4 lo = c, hi = c;
-#pragma unroll
-  for (int dy = 0; dy < 3; ++dy) {
-#pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      const float4 v = tile[ly + dy][lx + dx];
-      lo.x = fminf(lo.x, v.x); lo.y = fminf(lo.y, v.y); lo.z = fminf(lo.z, v.z); lo.w = fminf(lo.w, v.w);
-      hi.x = fmaxf(hi.x, v.x); hi.y = fmaxf(hi.y, v.y); hi.z = fmaxf(hi.z, v.z); hi.w = fmaxf(hi.w, v.w);
-    }
-  }
-  const size_t p = (size_t)py * W + px;
-  float4 h = hist[p];
-  h.x = fminf(fmaxf(h.x, lo.x), hi.x);
-  h.y = fminf(fmaxf(h.y, lo.y), hi.y);
-  h.z = fminf(fmaxf(h.z, lo.z), hi.z);
-  h.w = fminf(fmaxf(h.w, lo.w), hi.w);
-  out[p] = make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
-                       fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w));
-}
-
 __global__ __launch_bounds__(256) void jitter_kernel(const uint32_t* __restrict__ pxy, long long n,
                                                      uint32_t frame, uint32_t seed,
                                                      uint32_t* __restrict__ out) {
@@ -211,11 +179,6 @@ __global__ __launch_bounds__(256) void jitter_kernel(const uint32_t* __restrict_
   if (i < n) out[i] = (uint32_t)(jitter_offset(pxy[2 * i], pxy[2 * i + 1], frame, seed) * 16777216.0f);
 }
 
-__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
-                                                   float4* __restrict__ dst, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
-}
 
 // ---------------------------------------------------------------------------
 // Launchers: runtime (dtype, layout, detail, count) -> template instance
@@ -358,21 +321,6 @@ hipError_t launch_jitter(const uint32_t* pxy, long long n, uint32_t frame, uint3
                          uint32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(jitter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pxy, n,
                      frame, seed, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_taa(const float* cur, const float* hist, float* out, int W, int H, float blend,
-                      bool copy, hipStream_t s) {
-  if (copy) {
-    const long long n = (long long)W * H;
-    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       reinterpret_cast<const float4*>(cur), reinterpret_cast<float4*>(out), n);
-    return hipGetLastError();
-  }
-  const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
-  hipLaunchKernelGGL(taa_kernel, dim3(tiles_x * tiles_y), dim3(256), 0, s,
-                     reinterpret_cast<const float4*>(cur), reinterpret_cast<const float4*>(hist),
-                     reinterpret_cast<float4*>(out), W, H, tiles_x, blend);
   return hipGetLastError();
 }
 

@@ -178,8 +178,9 @@ constexpr int kSlots = 2;
 
 class HipExecutor : public serve::Executor {
  public:
-  HipExecutor(int device, const DevVolume& v, int dtype, int layout, float blend, bool graphs)
-      : device_(device), vol_(v), blend_(blend), graphs_(graphs) {
+  HipExecutor(int device, const DevVolume& v, int dtype, int layout, float blend, bool graphs,
+              int queues)
+      : device_(device), vol_(v), blend_(blend), graphs_(graphs), queues_(queues) {
     fn_ = pick(dtype, layout, v.detail != nullptr);
   }
 
@@ -195,8 +196,9 @@ class HipExecutor : public serve::Executor {
     if (e != hipSuccess || per_cu < 1) per_cu = 4;
     render_blocks_ = cus * per_cu;
     taa_blocks_ = cus * 4;
+    for (int q = 0; q < queues_; ++q)
+      if ((e = hipStreamCreateWithFlags(&stream_[q], hipStreamNonBlocking)) != hipSuccess) return err(e, msg);
     for (int s = 0; s < kSlots; ++s) {
-      if ((e = hipStreamCreateWithFlags(&stream_[s], hipStreamNonBlocking)) != hipSuccess) return err(e, msg);
       if ((e = hipEventCreateWithFlags(&event_[s], hipEventDisableTiming)) != hipSuccess) return err(e, msg);
       if ((e = hipHostMalloc(reinterpret_cast<void**>(&host_[s]), sizeof(ServeTable), hipHostMallocDefault)) != hipSuccess)
         return err(e, msg);
@@ -212,6 +214,8 @@ class HipExecutor : public serve::Executor {
     (void)hipSetDevice(device_);
     for (int s = 0; s < kSlots; ++s) {
       if (stream_[s]) (void)hipStreamSynchronize(stream_[s]);
+    }
+    for (int s = 0; s < kSlots; ++s) {
       if (exec_[s]) (void)hipGraphExecDestroy(exec_[s]);
       if (graph_[s]) (void)hipGraphDestroy(graph_[s]);
       if (dev_[s]) (void)hipFree(dev_[s]);
@@ -263,11 +267,11 @@ class HipExecutor : public serve::Executor {
     t->supertile = tuning().supertile;
     hipError_t e;
     if (graphs_) {
-      e = hipGraphLaunch(exec_[slot], stream_[slot]);
+      e = hipGraphLaunch(exec_[slot], queue(slot));
     } else {
       e = enqueue(slot);
     }
-    if (e == hipSuccess) e = hipEventRecord(event_[slot], stream_[slot]);
+    if (e == hipSuccess) e = hipEventRecord(event_[slot], queue(slot));
     return e == hipSuccess ? 0 : CLOUD_E_HIP;
   }
 
@@ -279,22 +283,29 @@ class HipExecutor : public serve::Executor {
   }
 
  private:
+  // Slots alternate over the queues. On one queue a batch's table copy is
+  // ordered after the previous batch; on two it can be issued while the
+  // previous persistent render still holds every CU and then waits for one.
+  hipStream_t queue(int slot) const { return stream_[slot % queues_]; }
+
   hipError_t enqueue(int slot) {
     // table (with zeroed counters) -> persistent render -> batched resolve
+    const hipStream_t q = queue(slot);
     hipError_t e = hipMemcpyAsync(dev_[slot], host_[slot], sizeof(ServeTable),
-                                  hipMemcpyHostToDevice, stream_[slot]);
+                                  hipMemcpyHostToDevice, q);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn_, dim3(render_blocks_), dim3(256), 0, stream_[slot], vol_, dev_[slot]);
+    hipLaunchKernelGGL(fn_, dim3(render_blocks_), dim3(256), 0, q, vol_, dev_[slot]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(serve_taa_kernel, dim3(taa_blocks_), dim3(256), 0, stream_[slot], dev_[slot]);
+    hipLaunchKernelGGL(serve_taa_kernel, dim3(taa_blocks_), dim3(256), 0, q, dev_[slot]);
     return hipGetLastError();
   }
 
   hipError_t capture(int slot) {
-    hipError_t e = hipStreamBeginCapture(stream_[slot], hipStreamCaptureModeThreadLocal);
+    const hipStream_t q = queue(slot);
+    hipError_t e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     const hipError_t le = enqueue(slot);
-    e = hipStreamEndCapture(stream_[slot], &graph_[slot]);
+    e = hipStreamEndCapture(q, &graph_[slot]);
     if (le != hipSuccess) return le;
     if (e != hipSuccess) return e;
     return hipGraphInstantiate(&exec_[slot], graph_[slot], nullptr, nullptr, 0);
@@ -309,6 +320,7 @@ class HipExecutor : public serve::Executor {
   DevVolume vol_;
   float blend_;
   bool graphs_;
+  int queues_;
   RenderFn fn_ = nullptr;
   int render_blocks_ = 0, taa_blocks_ = 0;
   hipStream_t stream_[kSlots] = {};
@@ -346,6 +358,7 @@ int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg
     if (cfg->max_batch < 1 || cfg->max_batch > kMaxBatch)
       return fail(CLOUD_E_INVALID, "max_batch must be in [1, 64]");
     if (cfg->max_queue < 1) return fail(CLOUD_E_INVALID, "max_queue must be >= 1");
+    if (cfg->queues < 0 || cfg->queues > kSlots) return fail(CLOUD_E_INVALID, "queues must be 0, 1 or 2");
     if (!std::isfinite(cfg->taa_blend) || !(cfg->taa_blend > 0.0f) || cfg->taa_blend > 1.0f)
       return fail(CLOUD_E_INVALID, "taa_blend must be in (0, 1]");
     int ndev = 0;
@@ -358,7 +371,7 @@ int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg
     auto srv = std::make_unique<cloud_server>();
     srv->volume = *shared;
     srv->ex = std::make_unique<HipExecutor>(cfg->device, v, dtype, shared->layout, cfg->taa_blend,
-                                            cfg->use_graphs != 0);
+                                            cfg->use_graphs != 0, cfg->queues == 0 ? 1 : cfg->queues);
     std::string msg;
     if ((rc = srv->ex->init(&msg))) return fail(rc, msg);
     serve::Config sc;

@@ -323,3 +323,20 @@ def test_abi_device_checks(cf, torch):
     with pytest.raises(cf.CloudError):
         cf.cloud_render(vol, w.camera(0), bad, 0, 8, 8)
     torch.cuda.synchronize()
+
+
+def test_c5_views_sampled(cf, torch):
+    w = scenes.workload("C5")
+    say(f"C5 {w.views} views of {w.width}x{w.height}, 512^3 f16 oct + occupancy: sampled parity per view")
+    sc = scenes.make_scene(w, dtype="f16")
+    vol = cf.device_volume(sc, layout="oct", occupancy=True)
+    cams = [w.camera(2, view=v) for v in range(w.views)]
+    img = cf.cloud_render_views(vol, cams, w.params, 2, w.width, w.height)
+    ovol = oracle_volume(sc)
+    for v in range(w.views):
+        pix = scenes.random_pixels(w.width, w.height, 512, seed=100 + v)
+        got = to_np(img[v])[pix[:, 1], pix[:, 0]]
+        want = O.render(ovol, cams[v], w.params, w.width, w.height, frame=2, pixels=pix)
+        assert max_err(got, want) < HALF_TOL, v
+    del img
+    torch.cuda.empty_cache()

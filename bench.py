@@ -101,6 +101,47 @@ def cpu_baseline(name: str, dtype: str, frames: int, cores: int) -> dict:
 
 
 # ---------------------------------------------------------------------------
+# Gather ceiling: the render's own fetches with the arithmetic removed
+# ---------------------------------------------------------------------------
+
+def gather_ceiling(cf, torch, np, w, vol, p, frames, render_ms: float, bytes_per_frame: float):
+    """Times cloud_gather_ceiling on the frames given: mode 0 replays exactly
+    the render's fetches (recorded by cloud_lookup_trace, outside the timed
+    launches), mode 1 makes as many lookups at uniformly random points of the
+    volume. The render's gather rate over mode 0's is the fraction of the
+    achievable rate for this access pattern."""
+    if p.steps > 32 or w.detail_n:
+        return None
+    V, W, H = w.views, w.width, w.height
+    frames = list(frames)
+    cams = {f: [w.camera(f, view=v) for v in range(V)] for f in frames}
+    traces = {f: cf.cloud_lookup_trace(vol, cams[f], p, f, W, H) for f in frames}
+    out = torch.empty((V, H, W, 4), device="cuda")
+    ms = {}
+    for mode in (0, 1):
+        cf.cloud_gather_ceiling(vol, cams[frames[0]], p, frames[0], W, H, traces[frames[0]], mode,
+                                out=out)
+        torch.cuda.synchronize()
+        ev = []
+        for f in frames:     # launched back to back, like the render frames
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            cf.cloud_gather_ceiling(vol, cams[f], p, f, W, H, traces[f], mode, out=out)
+            b.record()
+            ev.append((a, b))
+        torch.cuda.synchronize()
+        ms[mode] = [a.elapsed_time(b) for a, b in ev]
+    same, rand = float(np.mean(ms[0])), float(np.mean(ms[1]))
+    del traces
+    return {"kernel": "gather_ceiling_kernel", "frames": len(ms[0]),
+            "same_positions_ms": round(same, 4), "random_positions_ms": round(rand, 4),
+            "render_ms": round(render_ms, 4),
+            "ceiling_GBps": round(bytes_per_frame / (same * 1e-3) / 1e9, 1),
+            "random_GBps": round(bytes_per_frame / (rand * 1e-3) / 1e9, 1),
+            "frac_of_ceiling": round(same / render_ms, 4)}
+
+
+# ---------------------------------------------------------------------------
 # Served form: many camera streams through cloud_serve_* (closed loop)
 # ---------------------------------------------------------------------------
 
@@ -299,6 +340,8 @@ def main():
     ap.add_argument("--served-dtype", default="f16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--served-layout", default="oct", choices=["dense", "quad", "oct"])
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the gather-ceiling measurement")
     ap.add_argument("--serve-queues", type=int, default=1, choices=[1, 2])
     ap.add_argument("--no-occupancy", action="store_true",
                     help="render without the exact empty-space-skipping bitmap")
@@ -446,6 +489,10 @@ def main():
                                      "this kernel source and config (null if either changed)"},
         "cpu_baseline": cpu,
     }
+    if not args.no_ceiling:
+        line["gather_ceiling"] = gather_ceiling(cf, torch, np, w, vol, p,
+                                                range(args.warmup, total)[:20], render_ms,
+                                                lk_frame * bytes_per_lookup)
     if not args.no_served:
         del cur, hist, vol
         torch.cuda.empty_cache()

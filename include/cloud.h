@@ -207,6 +207,35 @@ int cloud_count_lookups(const cloud_volume* volume, const cloud_camera* camera,
                         int32_t width, int32_t height, uint64_t* out_count,
                         void* hip_stream);
 
+/* Records which lookups cloud_render_views performs for these views and
+ * this frame: out_trace (device [n_views][height][width][2] uint32, 8-byte
+ * aligned, caller-owned) gets per pixel the number of primary samples taken
+ * (up to the early exit, Section 1) and a mask whose bit i is set when
+ * sample i ran the light march (density > 0). Requires params->steps <= 32.
+ * Writes no image. Input to cloud_gather_ceiling. */
+int cloud_lookup_trace(const cloud_volume* volume, const cloud_camera* cameras,
+                       int32_t n_views, const cloud_params* params,
+                       uint32_t frame_index, int32_t width, int32_t height,
+                       uint32_t* out_trace, void* hip_stream);
+
+/* Measurement only: the render's gather pattern without its arithmetic.
+ * One thread per pixel on the render's launch shape and tile walk.
+ *  mode 0: fetches exactly the volume words cloud_render_views fetches for
+ *          the lookups recorded in trace (same footprints, same order, same
+ *          occupancy skip), with no interpolation, lighting or integration;
+ *  mode 1: the same number of lookups per pixel at uniformly random texel
+ *          coordinates of the whole volume (no occupancy skip).
+ * out_rgba (device [n_views][height][width][4] float32, 16-byte aligned)
+ * gets an XOR of the fetched words in .x (no meaning; it keeps every fetch)
+ * and zeros. trace: as written by cloud_lookup_trace with the same volume,
+ * cameras, params and frame. No detail volume; params->steps <= 32. Loop
+ * counts are bounded by the step counts whatever trace holds. */
+int cloud_gather_ceiling(const cloud_volume* volume, const cloud_camera* cameras,
+                         int32_t n_views, const cloud_params* params,
+                         uint32_t frame_index, int32_t width, int32_t height,
+                         const uint32_t* trace, int32_t mode, float* out_rgba,
+                         void* hip_stream);
+
 /* Device bytes a copy of the dense volume's base needs in `layout`. */
 int cloud_volume_packed_bytes(const cloud_volume* dense, int32_t layout,
                               uint64_t* bytes);
@@ -240,8 +269,11 @@ int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t ds
  * not depend on it. Keys: "supertile" (0..64, default 4) -- the render walks
  * its 16x16-pixel tiles in S x S super-tiles so that the tiles an XCD works on
  * together cover a compact patch of the image (0 = row-major); "taa_tile"
- * (16, 32 or 64, default 16) -- the resolve's tile width in pixels (each
- * tile holds 256 pixels). */
+ * (16, 32 or 64, default 32) -- the resolve's tile width in pixels (each
+ * tile holds 256 pixels); "render_blocks_per_cu" -- at most this many render
+ * workgroups resident per CU, enforced by reserving LDS at launch
+ * (CLOUD_E_INVALID when the device's LDS cannot express it); 0 = no cap;
+ * -1 (default) = 3 for float32 quad/oct volumes, no cap otherwise. */
 int cloud_tune(const char* key, int32_t value);
 
 /* Checks that [ptr, ptr + bytes) lies inside one HIP device allocation: the

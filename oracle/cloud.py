@@ -239,13 +239,16 @@ def light_transmittance(vol: OracleVolume, p, s_hat, light_steps: int, alpha: fl
 # ---------------------------------------------------------------------------
 
 def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
-               return_lookups: bool = False):
+               return_lookups: bool = False, return_trace: bool = False):
     """March n rays; returns RGBA [n,4] (premultiplied colour, alpha = 1 - T).
 
     origins, dirs: [n,3] (dirs need not be unit length; they are normalised).
     jitter: per-ray offsets j in [0,1), or None for j = 0.5 (R6).
     params: steps, light_steps, alpha, g, sun_dir, sun_color, ambient,
             integration (0 naive, 1 analytic), t_eps.
+    return_lookups adds the number of density lookups performed; return_trace
+    adds, per ray, the primary samples taken and a mask with bit i set when
+    sample i ran the light march.
     Each primary step (Section 1): sample rho, march towards the sun for the
     incident light, add the ambient term, integrate over the step (Section
     3.1), update T, stop once T < t_eps (R12)."""
@@ -267,6 +270,8 @@ def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
     S = np.zeros((n, 3))
     alive = hit.copy()
     lookups = 0
+    prim = np.zeros(n, dtype=np.int64)
+    mask = np.zeros(n, dtype=np.uint64)
     for i in range(N):
         idx = np.nonzero(alive)[0]
         if idx.size == 0:
@@ -275,11 +280,14 @@ def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
         p = o[idx] + t[:, None] * d[idx]
         rho = density(vol, p)
         lookups += idx.size
+        prim[idx] += 1
         TL = np.ones(idx.size)
         lit = rho > 0.0
         if L > 0 and lit.any():
             TL[lit] = light_transmittance(vol, p[lit], s_hat, L, alpha)
             lookups += L * int(lit.sum())
+            if i < 64:
+                mask[idx[lit]] |= np.uint64(1) << np.uint64(i)
         L_in = c_sun[None, :] * (phase[idx] * TL)[:, None] + c_amb[None, :]
         x = rho * alpha * D[idx]
         if int(params.integration) == 1:
@@ -295,17 +303,18 @@ def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
             alive[idx] = T[idx] >= eps
     rgba = np.concatenate([S, (1.0 - T)[:, None]], axis=1)
     rgba[~hit] = 0.0
-    if return_lookups:
-        return rgba, lookups
-    return rgba
+    extra = ([lookups] if return_lookups else []) + ([(prim, mask)] if return_trace else [])
+    return (rgba, *extra) if extra else rgba
 
 
 def render(vol: OracleVolume, cam, params, width: int, height: int, frame: int = 0,
-           pixels=None, return_lookups: bool = False):
+           pixels=None, return_lookups: bool = False, return_trace: bool = False):
     """Render the cloud layer (RGBA premultiplied, no background; R15).
 
     pixels: None for the whole image ([height, width, 4] result), or an
-    [n,2] array of (px, py) for those pixels only ([n,4] result)."""
+    [n,2] array of (px, py) for those pixels only ([n,4] result).
+    return_lookups / return_trace: as in march_rays (the trace per pixel, in
+    the result's pixel order)."""
     if pixels is None:
         py, px = np.meshgrid(np.arange(height), np.arange(width), indexing="ij")
         px, py = px.reshape(-1), py.reshape(-1)
@@ -314,11 +323,14 @@ def render(vol: OracleVolume, cam, params, width: int, height: int, frame: int =
         px, py = pixels[:, 0], pixels[:, 1]
     o, d = camera_rays(cam, width, height, px, py)
     j = jitter_offset(px, py, frame, int(params.seed)) if int(params.jitter) else None
-    out = march_rays(vol, o, d, params, jitter=j, return_lookups=return_lookups)
-    rgba, lk = out if return_lookups else (out, None)
+    out = march_rays(vol, o, d, params, jitter=j, return_lookups=return_lookups,
+                     return_trace=return_trace)
+    if not (return_lookups or return_trace):
+        out = (out,)
+    rgba = out[0]
     if pixels is None:
         rgba = rgba.reshape(height, width, 4)
-    return (rgba, lk) if return_lookups else rgba
+    return (rgba, *out[1:]) if len(out) > 1 else rgba
 
 
 # ---------------------------------------------------------------------------

@@ -12,6 +12,8 @@ from ._lib import (  # noqa: F401
     Volume,
     cloud_check_buffer,
     cloud_count_lookups,
+    cloud_lookup_trace,
+    cloud_gather_ceiling,
     cloud_jitter_offsets,
     cloud_march_rays,
     cloud_render,

@@ -91,11 +91,18 @@ def load():
     lib.cloud_count_lookups.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera),
                                         POINTER(cloud_params), c_uint32, c_int32, c_int32,
                                         c_void_p, c_void_p]
+    lib.cloud_lookup_trace.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,
+                                       POINTER(cloud_params), c_uint32, c_int32, c_int32,
+                                       c_void_p, c_void_p]
+    lib.cloud_gather_ceiling.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,
+                                         POINTER(cloud_params), c_uint32, c_int32, c_int32,
+                                         c_void_p, c_int32, c_void_p, c_void_p]
     lib.cloud_volume_packed_bytes.argtypes = [POINTER(cloud_volume), c_int32, POINTER(c_uint64)]
     lib.cloud_volume_pack.argtypes = [POINTER(cloud_volume), c_int32, c_void_p, c_uint64,
                                       POINTER(cloud_volume), c_void_p]
     for name in ("cloud_render", "cloud_render_views", "cloud_march_rays", "cloud_taa_resolve",
                  "cloud_jitter_offsets", "cloud_check_buffer", "cloud_count_lookups",
+                 "cloud_lookup_trace", "cloud_gather_ceiling",
                  "cloud_volume_packed_bytes", "cloud_volume_pack", "cloud_tune"):
         getattr(lib, name).restype = c_int
     _lib = lib
@@ -238,6 +245,36 @@ def cloud_count_lookups(volume: Volume, camera, params, frame_index: int, width:
     check(load().cloud_count_lookups(ctypes.byref(volume.struct), ctypes.byref(cam),
                                      ctypes.byref(prm), int(frame_index) & 0xFFFFFFFF, int(width),
                                      int(height), _ptr(out), _stream(stream)))
+    return out
+
+
+def cloud_lookup_trace(volume: Volume, cameras, params, frame_index: int, width: int, height: int,
+                       out=None, stream=None):
+    """Per-pixel (primary samples, light-march mask) of a render of these views:
+    device int32 tensor [n_views, H, W, 2] (the bits are uint32)."""
+    import torch
+    n = len(cameras)
+    if out is None:
+        out = torch.empty((n, height, width, 2), dtype=torch.int32, device=volume.base.device)
+    cams = (cloud_camera * max(n, 1))(*[make_camera(c) for c in cameras])
+    prm = make_params(params)
+    check(load().cloud_lookup_trace(ctypes.byref(volume.struct), cams, n, ctypes.byref(prm),
+                                    int(frame_index) & 0xFFFFFFFF, int(width), int(height),
+                                    _ptr(out), _stream(stream)))
+    return out
+
+
+def cloud_gather_ceiling(volume: Volume, cameras, params, frame_index: int, width: int,
+                         height: int, trace, mode: int = 0, out=None, stream=None):
+    """Fetch-only replay of the render's lookups (mode 0) or as many uniformly
+    random lookups (mode 1); returns the [n_views, H, W, 4] output buffer."""
+    n = len(cameras)
+    out = _out(out, (n, height, width, 4), volume.base.device)
+    cams = (cloud_camera * max(n, 1))(*[make_camera(c) for c in cameras])
+    prm = make_params(params)
+    check(load().cloud_gather_ceiling(ctypes.byref(volume.struct), cams, n, ctypes.byref(prm),
+                                      int(frame_index) & 0xFFFFFFFF, int(width), int(height),
+                                      _ptr(trace), int(mode), _ptr(out), _stream(stream)))
     return out
 
 

@@ -285,7 +285,8 @@ int cloud_abi_version(void) { return CLOUD_ABI_VERSION; }
 
 static int render_impl(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
                        const cloud_params* params, uint32_t frame_index, int32_t width,
-                       int32_t height, float* out_rgba, uint64_t* counts, void* hip_stream) {
+                       int32_t height, float* out_rgba, uint64_t* counts, uint32_t* trace,
+                       void* hip_stream) {
   clear_error();
   if (!cameras) return fail(CLOUD_E_INVALID, "cameras is NULL");
   if (n_views < 1) return fail(CLOUD_E_INVALID, "n_views must be >= 1");
@@ -297,10 +298,18 @@ static int render_impl(const cloud_volume* volume, const cloud_camera* cameras, 
   DevParams p;
   if ((rc = prepare_params(params, volume, &p))) return rc;
   const size_t px = (size_t)width * height;
-  if (counts) {
-    if (reinterpret_cast<uintptr_t>(counts) % 8)
-      return fail(CLOUD_E_INVALID, "out_count must be 8-byte aligned");
-    if ((rc = check_span(counts, 8, "out_count"))) return rc;
+  if (counts || trace) {
+    if (counts) {
+      if (reinterpret_cast<uintptr_t>(counts) % 8)
+        return fail(CLOUD_E_INVALID, "out_count must be 8-byte aligned");
+      if ((rc = check_span(counts, 8, "out_count"))) return rc;
+    }
+    if (trace) {
+      if (params->steps > 32) return fail(CLOUD_E_INVALID, "a lookup trace needs steps <= 32");
+      if (reinterpret_cast<uintptr_t>(trace) % 8)
+        return fail(CLOUD_E_INVALID, "out_trace must be 8-byte aligned");
+      if ((rc = check_span(trace, px * 8 * (size_t)n_views, "out_trace"))) return rc;
+    }
   } else {
     if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
       return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
@@ -313,9 +322,11 @@ static int render_impl(const cloud_volume* volume, const cloud_camera* cameras, 
     if ((i + 1) % kMaxViews == 0 || last) {
       const int first = i - i % kMaxViews;
       const int count = i - first + 1;
+      const bool image = !counts && !trace;
       hipError_t e = launch_render(v, dtype, volume->layout, p, cams, count, frame_index, width,
-                                   height, counts ? nullptr : out_rgba + (size_t)first * px * 4,
+                                   height, image ? out_rgba + (size_t)first * px * 4 : nullptr,
                                    reinterpret_cast<unsigned long long*>(counts),
+                                   trace ? trace + (size_t)first * px * 2 : nullptr,
                                    static_cast<hipStream_t>(hip_stream));
       if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("render launch: ") + hipGetErrorString(e));
     }
@@ -328,7 +339,7 @@ int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras, 
                        int32_t height, float* out_rgba, void* hip_stream) {
   CLOUD_GUARD_BEGIN
   return render_impl(volume, cameras, n_views, params, frame_index, width, height, out_rgba,
-                     nullptr, hip_stream);
+                     nullptr, nullptr, hip_stream);
   CLOUD_GUARD_END
 }
 
@@ -338,7 +349,59 @@ int cloud_count_lookups(const cloud_volume* volume, const cloud_camera* camera,
   CLOUD_GUARD_BEGIN
   if (!out_count) return fail(CLOUD_E_INVALID, "out_count is NULL");
   return render_impl(volume, camera, 1, params, frame_index, width, height, nullptr, out_count,
-                     hip_stream);
+                     nullptr, hip_stream);
+  CLOUD_GUARD_END
+}
+
+int cloud_lookup_trace(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
+                       const cloud_params* params, uint32_t frame_index, int32_t width,
+                       int32_t height, uint32_t* out_trace, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  if (!out_trace) return fail(CLOUD_E_INVALID, "out_trace is NULL");
+  if (!params) return fail(CLOUD_E_INVALID, "params is NULL");
+  return render_impl(volume, cameras, n_views, params, frame_index, width, height, nullptr,
+                     nullptr, out_trace, hip_stream);
+  CLOUD_GUARD_END
+}
+
+int cloud_gather_ceiling(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
+                         const cloud_params* params, uint32_t frame_index, int32_t width,
+                         int32_t height, const uint32_t* trace, int32_t mode, float* out_rgba,
+                         void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (!cameras) return fail(CLOUD_E_INVALID, "cameras is NULL");
+  if (n_views < 1) return fail(CLOUD_E_INVALID, "n_views must be >= 1");
+  if (mode != 0 && mode != 1) return fail(CLOUD_E_INVALID, "mode must be 0 or 1");
+  int rc = check_image(width, height, n_views);
+  if (rc) return rc;
+  if (!volume) return fail(CLOUD_E_INVALID, "volume is NULL");
+  if (volume->detail) return fail(CLOUD_E_INVALID, "the gather ceiling takes no detail volume");
+  DevVolume v;
+  int dtype;
+  if ((rc = prepare_volume(volume, &v, &dtype))) return rc;
+  DevParams p;
+  if ((rc = prepare_params(params, volume, &p))) return rc;
+  if (params->steps > 32) return fail(CLOUD_E_INVALID, "a lookup trace needs steps <= 32");
+  const size_t px = (size_t)width * height;
+  if (reinterpret_cast<uintptr_t>(trace) % 8) return fail(CLOUD_E_INVALID, "trace must be 8-byte aligned");
+  if ((rc = check_span(trace, px * 8 * (size_t)n_views, "trace"))) return rc;
+  if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
+    return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
+  if ((rc = check_span(out_rgba, px * 16 * (size_t)n_views, "out_rgba"))) return rc;
+  DevCameras cams;
+  for (int i = 0; i < n_views; ++i) {
+    if ((rc = prepare_camera(&cameras[i], width, height, &cams.c[i % kMaxViews]))) return rc;
+    if ((i + 1) % kMaxViews == 0 || i + 1 == n_views) {
+      const int first = i - i % kMaxViews;
+      hipError_t e = launch_ceiling(v, dtype, volume->layout, p, cams, i - first + 1, frame_index,
+                                    width, height, trace + (size_t)first * px * 2, mode == 1,
+                                    out_rgba + (size_t)first * px * 4,
+                                    static_cast<hipStream_t>(hip_stream));
+      if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("ceiling launch: ") + hipGetErrorString(e));
+    }
+  }
+  return CLOUD_OK;
   CLOUD_GUARD_END
 }
 
@@ -536,6 +599,14 @@ int cloud_tune(const char* key, int32_t value) {
     if (value != 16 && value != 32 && value != 64)
       return fail(CLOUD_E_INVALID, "taa_tile must be 16, 32 or 64");
     tuning().taa_tile = value;
+    return CLOUD_OK;
+  }
+  if (k == "render_blocks_per_cu") {
+    if (value < -1 || value > 64)
+      return fail(CLOUD_E_INVALID, "render_blocks_per_cu must be -1 (automatic) or in [0, 64]");
+    if (value > 0 && residency_lds(value, 4096) < 0)
+      return fail(CLOUD_E_INVALID, "render_blocks_per_cu: this cap cannot be set through LDS");
+    tuning().render_blocks_per_cu = value;
     return CLOUD_OK;
   }
   return fail(CLOUD_E_INVALID, "unknown tuning key " + k);

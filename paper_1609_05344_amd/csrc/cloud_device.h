@@ -122,6 +122,11 @@ __device__ __forceinline__ bool occupied(const DevVolume& v, int kx, int ky, int
 
 // ---------------------------------------------------------------------------
 // Base-volume trilinear lookup with clamp-to-edge, x then y then z
+//
+// Each layout fetches the words of one footprint (load) and turns them into
+// the eight texels in the order (x0,y0,z0), (x1,y0,z0), (x0,y1,z0), (x1,y1,z0),
+// then the same four of plane z1 (decode). A dead lookup (empty brick) keeps
+// its fetches but points them at entry 0.
 // ---------------------------------------------------------------------------
 
 template <int DT, int LAYOUT>
@@ -130,29 +135,33 @@ struct BaseSampler;
 // Dense [nz][ny][nx]: eight texel fetches per lookup.
 template <int DT>
 struct BaseSampler<DT, LAYOUT_DENSE> {
-  __device__ static __forceinline__ float fetch(const DevVolume& v, float fx, float fy, float fz) {
-    float wx, wy, wz;
-    int kx, ky, kz;
-    split_coord(fx, v.nx, wx, kx);
-    split_coord(fy, v.ny, wy, ky);
-    split_coord(fz, v.nz, wz, kz);
-    const bool live = occupied(v, kx, ky, kz);
-    CLOUD_SKIP_DEAD(live);
+  static constexpr int kWords = 8;
+  __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
+                                              uint32_t (&w)[kWords]) {
     const int xa = min(max(kx, 0), v.nx - 1), xb = min(max(kx + 1, 0), v.nx - 1);
     const int ya = min(max(ky, 0), v.ny - 1), yb = min(max(ky + 1, 0), v.ny - 1);
     const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
     // indices stay below 2^31 and plane < 2^24 (checked on the host), so the
-    // 24-bit multiplies are exact; a dead lookup reads texel 0 instead
+    // 24-bit multiplies are exact
     const int ra = __umul24(ya, v.row), rb = __umul24(yb, v.row);
     const int pa = __umul24(za, v.plane), pb = __umul24(zb, v.plane);
     const int i0 = live ? pa + ra : 0, i1 = live ? pa + rb : 0;
     const int i2 = live ? pb + ra : 0, i3 = live ? pb + rb : 0;
     const int x0 = live ? xa : 0, x1 = live ? xb : 0;
-    const float c00 = lerp(texel<DT>(v.base, i0 + x0), texel<DT>(v.base, i0 + x1), wx);
-    const float c10 = lerp(texel<DT>(v.base, i1 + x0), texel<DT>(v.base, i1 + x1), wx);
-    const float c01 = lerp(texel<DT>(v.base, i2 + x0), texel<DT>(v.base, i2 + x1), wx);
-    const float c11 = lerp(texel<DT>(v.base, i3 + x0), texel<DT>(v.base, i3 + x1), wx);
-    return live ? lerp(lerp(c00, c10, wy), lerp(c01, c11, wy), wz) : 0.0f;
+    const int idx[8] = {i0 + x0, i0 + x1, i1 + x0, i1 + x1, i2 + x0, i2 + x1, i3 + x0, i3 + x1};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if constexpr (DT == DT_F32) w[k] = static_cast<const uint32_t*>(v.base)[idx[k]];
+      else w[k] = static_cast<const uint16_t*>(v.base)[idx[k]];
+    }
+  }
+  __device__ static __forceinline__ void decode(const uint32_t (&w)[kWords], float (&c)[8]) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if constexpr (DT == DT_F32) c[k] = __uint_as_float(w[k]);
+      else if constexpr (DT == DT_F16) c[k] = (float)__builtin_bit_cast(_Float16, (uint16_t)w[k]);
+      else c[k] = __uint_as_float(w[k] << 16);
+    }
   }
 };
 
@@ -161,40 +170,44 @@ __device__ __forceinline__ int packed_xy(const DevVolume& v, int kx, int ky) {
   return __umul24(min(ky, v.ny - 1) + 1, v.row) + min(kx, v.nx - 1) + 1;
 }
 
+// Four float32 texels, or eight 16-bit texels packed two to a word (low half
+// first), to floats.
+template <int DT, int N>
+__device__ __forceinline__ void decode_packed(const uint32_t (&w)[N], float (&c)[8]) {
+  if constexpr (DT == DT_F32) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = __uint_as_float(w[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) unpack2<DT>(w[k], c[2 * k], c[2 * k + 1]);
+  }
+}
+
 // Quad layout [nz][ny+1][nx+1] x 4: entry (z, y, x) holds the texels at
 // (x, y), (x+1, y), (x, y+1), (x+1, y+1) of plane z (edge-clamped), so a
 // lookup is two aligned fetches, one per z plane.
 template <int DT>
 struct BaseSampler<DT, LAYOUT_QUAD> {
-  __device__ static __forceinline__ float fetch(const DevVolume& v, float fx, float fy, float fz) {
-    float wx, wy, wz;
-    int kx, ky, kz;
-    split_coord(fx, v.nx, wx, kx);
-    split_coord(fy, v.ny, wy, ky);
-    split_coord(fz, v.nz, wz, kz);
-    const bool live = occupied(v, kx, ky, kz);
-    CLOUD_SKIP_DEAD(live);
+  static constexpr int kWords = DT == DT_F32 ? 8 : 4;
+  __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
+                                              uint32_t (&w)[kWords]) {
     const int e = packed_xy(v, kx, ky);
     const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
     const int ea = live ? __umul24(za, v.plane) + e : 0;
     const int eb = live ? __umul24(zb, v.plane) + e : 0;
-    float a0, a1, a2, a3, b0, b1, b2, b3;
     if constexpr (DT == DT_F32) {
-      const float4* q = static_cast<const float4*>(v.base);
-      const float4 A = q[ea], B = q[eb];
-      a0 = A.x; a1 = A.y; a2 = A.z; a3 = A.w;
-      b0 = B.x; b1 = B.y; b2 = B.z; b3 = B.w;
+      const uint4* q = static_cast<const uint4*>(v.base);
+      const uint4 A = q[ea], B = q[eb];
+      w[0] = A.x; w[1] = A.y; w[2] = A.z; w[3] = A.w;
+      w[4] = B.x; w[5] = B.y; w[6] = B.z; w[7] = B.w;
     } else {
       const uint2* q = static_cast<const uint2*>(v.base);
       const uint2 A = q[ea], B = q[eb];
-      unpack2<DT>(A.x, a0, a1);
-      unpack2<DT>(A.y, a2, a3);
-      unpack2<DT>(B.x, b0, b1);
-      unpack2<DT>(B.y, b2, b3);
+      w[0] = A.x; w[1] = A.y; w[2] = B.x; w[3] = B.y;
     }
-    const float c0 = lerp(lerp(a0, a1, wx), lerp(a2, a3, wx), wy);
-    const float c1 = lerp(lerp(b0, b1, wx), lerp(b2, b3, wx), wy);
-    return live ? lerp(c0, c1, wz) : 0.0f;
+  }
+  __device__ static __forceinline__ void decode(const uint32_t (&w)[kWords], float (&c)[8]) {
+    decode_packed<DT>(w, c);
   }
 };
 
@@ -203,33 +216,44 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
 // so a lookup is one aligned fetch (two for float32).
 template <int DT>
 struct BaseSampler<DT, LAYOUT_OCT> {
-  __device__ static __forceinline__ float fetch(const DevVolume& v, float fx, float fy, float fz) {
-    float wx, wy, wz;
-    int kx, ky, kz;
-    split_coord(fx, v.nx, wx, kx);
-    split_coord(fy, v.ny, wy, ky);
-    split_coord(fz, v.nz, wz, kz);
-    const bool live = occupied(v, kx, ky, kz);
-    CLOUD_SKIP_DEAD(live);
+  static constexpr int kWords = DT == DT_F32 ? 8 : 4;
+  __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
+                                              uint32_t (&w)[kWords]) {
     const int e = live ? __umul24(min(kz, v.nz - 1) + 1, v.plane) + packed_xy(v, kx, ky) : 0;
-    float a0, a1, a2, a3, b0, b1, b2, b3;
     if constexpr (DT == DT_F32) {
-      const float4* q = static_cast<const float4*>(v.base) + 2 * (size_t)e;
-      const float4 A = q[0], B = q[1];
-      a0 = A.x; a1 = A.y; a2 = A.z; a3 = A.w;
-      b0 = B.x; b1 = B.y; b2 = B.z; b3 = B.w;
+      const uint4* q = static_cast<const uint4*>(v.base) + 2 * (size_t)e;
+      const uint4 A = q[0], B = q[1];
+      w[0] = A.x; w[1] = A.y; w[2] = A.z; w[3] = A.w;
+      w[4] = B.x; w[5] = B.y; w[6] = B.z; w[7] = B.w;
     } else {
       const uint4 Q = static_cast<const uint4*>(v.base)[e];
-      unpack2<DT>(Q.x, a0, a1);
-      unpack2<DT>(Q.y, a2, a3);
-      unpack2<DT>(Q.z, b0, b1);
-      unpack2<DT>(Q.w, b2, b3);
+      w[0] = Q.x; w[1] = Q.y; w[2] = Q.z; w[3] = Q.w;
     }
-    const float c0 = lerp(lerp(a0, a1, wx), lerp(a2, a3, wx), wy);
-    const float c1 = lerp(lerp(b0, b1, wx), lerp(b2, b3, wx), wy);
-    return live ? lerp(c0, c1, wz) : 0.0f;
+  }
+  __device__ static __forceinline__ void decode(const uint32_t (&w)[kWords], float (&c)[8]) {
+    decode_packed<DT>(w, c);
   }
 };
+
+// Trilinear lookup of the base volume at continuous texel coordinates f.
+template <int DT, int LAYOUT>
+__device__ __forceinline__ float base_lookup(const DevVolume& v, float fx, float fy, float fz) {
+  using S = BaseSampler<DT, LAYOUT>;
+  float wx, wy, wz;
+  int kx, ky, kz;
+  split_coord(fx, v.nx, wx, kx);
+  split_coord(fy, v.ny, wy, ky);
+  split_coord(fz, v.nz, wz, kz);
+  const bool live = occupied(v, kx, ky, kz);
+  CLOUD_SKIP_DEAD(live);
+  uint32_t w[S::kWords];
+  S::load(v, kx, ky, kz, live, w);
+  float c[8];
+  S::decode(w, c);
+  const float c0 = lerp(lerp(c[0], c[1], wx), lerp(c[2], c[3], wx), wy);
+  const float c1 = lerp(lerp(c[4], c[5], wx), lerp(c[6], c[7], wx), wy);
+  return live ? lerp(c0, c1, wz) : 0.0f;
+}
 
 // Index k of a periodic axis of n texels, wrapped into [0, n).
 __device__ __forceinline__ int wrap_index(int k, int n) {
@@ -311,7 +335,7 @@ __device__ __forceinline__ float detail_oct(const DevVolume& v, float fx, float 
 template <int DT, int LAYOUT, bool DETAIL>
 __device__ __forceinline__ float density_tex(const DevVolume& v, float fx, float fy, float fz,
                                              float gx, float gy, float gz) {
-  const float b = BaseSampler<DT, LAYOUT>::fetch(v, fx, fy, fz);
+  const float b = base_lookup<DT, LAYOUT>(v, fx, fy, fz);
   if constexpr (!DETAIL) {
     return b;
   } else {
@@ -335,55 +359,69 @@ __device__ __forceinline__ float density(const DevVolume& v, float px, float py,
                                            fmaf(pz, v.sz, v.oz), 0.0f, 0.0f, 0.0f);
 }
 
-// Transmittance towards the sun from p (Section 1): L midpoint samples of
-// equal steps up to the box exit along s, Beer-Lambert over their sum. The
-// sample points are stepped in texel coordinates directly (the map from world
-// to texel coordinates is affine).
-template <int DT, int LAYOUT, bool DETAIL>
-__device__ __forceinline__ float light_transmittance(const DevVolume& v, const DevParams& P,
-                                                     float px, float py, float pz) {
+// Sample points of the light march from p (Section 1): L midpoints of equal
+// steps up to the box exit along s, as continuous texel coordinates of the
+// base (f0 + h df) and of the detail (g0 + h dg), h = k + 1/2, and the step
+// length dl. The map from world to texel coordinates is affine, so the points
+// are stepped in texel coordinates directly.
+struct LightPath {
+  float fx0, fy0, fz0, dfx, dfy, dfz;
+  float gx0, gy0, gz0, dgx, dgy, dgz;
+  float dl;
+};
+
+template <bool DETAIL>
+__device__ __forceinline__ LightPath light_path(const DevVolume& v, const DevParams& P, float px,
+                                                float py, float pz) {
   float tx = 3.402823466e38f;
   if (P.s_axis[0]) tx = fminf(tx, (P.light_bound[0] - px) * P.inv_s[0]);
   if (P.s_axis[1]) tx = fminf(tx, (P.light_bound[1] - py) * P.inv_s[1]);
   if (P.s_axis[2]) tx = fminf(tx, (P.light_bound[2] - pz) * P.inv_s[2]);
-  const float dl = tx * P.inv_light_steps;
-  const float stx = dl * P.s[0], sty = dl * P.s[1], stz = dl * P.s[2];
-  const float fx0 = fmaf(px, v.sx, v.ox), fy0 = fmaf(py, v.sy, v.oy), fz0 = fmaf(pz, v.sz, v.oz);
-  const float dfx = stx * v.sx, dfy = sty * v.sy, dfz = stz * v.sz;
-  float gx0 = 0.0f, gy0 = 0.0f, gz0 = 0.0f, dgx = 0.0f, dgy = 0.0f, dgz = 0.0f;
+  LightPath lp;
+  lp.dl = tx * P.inv_light_steps;
+  const float stx = lp.dl * P.s[0], sty = lp.dl * P.s[1], stz = lp.dl * P.s[2];
+  lp.fx0 = fmaf(px, v.sx, v.ox);
+  lp.fy0 = fmaf(py, v.sy, v.oy);
+  lp.fz0 = fmaf(pz, v.sz, v.oz);
+  lp.dfx = stx * v.sx;
+  lp.dfy = sty * v.sy;
+  lp.dfz = stz * v.sz;
+  lp.gx0 = lp.gy0 = lp.gz0 = lp.dgx = lp.dgy = lp.dgz = 0.0f;
   if constexpr (DETAIL) {
-    gx0 = fmaf(px, v.dsx, v.dox);
-    gy0 = fmaf(py, v.dsy, v.doy);
-    gz0 = fmaf(pz, v.dsz, v.doz);
-    dgx = stx * v.dsx;
-    dgy = sty * v.dsy;
-    dgz = stz * v.dsz;
+    lp.gx0 = fmaf(px, v.dsx, v.dox);
+    lp.gy0 = fmaf(py, v.dsy, v.doy);
+    lp.gz0 = fmaf(pz, v.dsz, v.doz);
+    lp.dgx = stx * v.dsx;
+    lp.dgy = sty * v.dsy;
+    lp.dgz = stz * v.dsz;
   }
+  return lp;
+}
+
+// Transmittance towards the sun from p (Section 1): Beer-Lambert over the
+// sum of the light-march samples.
+template <int DT, int LAYOUT, bool DETAIL>
+__device__ __forceinline__ float light_transmittance(const DevVolume& v, const DevParams& P,
+                                                     float px, float py, float pz) {
+  const LightPath lp = light_path<DETAIL>(v, P, px, py, pz);
   float acc = 0.0f;
 #pragma unroll kLightUnroll
   for (int k = 0; k < P.light_steps; ++k) {
     const float h = (float)k + 0.5f;
-    acc += density_tex<DT, LAYOUT, DETAIL>(v, fmaf(h, dfx, fx0), fmaf(h, dfy, fy0),
-                                           fmaf(h, dfz, fz0), fmaf(h, dgx, gx0),
-                                           fmaf(h, dgy, gy0), fmaf(h, dgz, gz0));
+    acc += density_tex<DT, LAYOUT, DETAIL>(v, fmaf(h, lp.dfx, lp.fx0), fmaf(h, lp.dfy, lp.fy0),
+                                           fmaf(h, lp.dfz, lp.fz0), fmaf(h, lp.dgx, lp.gx0),
+                                           fmaf(h, lp.dgy, lp.gy0), fmaf(h, lp.dgz, lp.gz0));
   }
-  return exp2f(-P.alpha_log2e * dl * acc);
+  return exp2f(-P.alpha_log2e * lp.dl * acc);
 }
 
-struct RayResult {
-  float r, g, b, a;
-  uint32_t lookups;   // density lookups performed (counted only on request)
-};
-
-// One primary ray through the volume (Sections 1, 3.1, 3.2). (o, d): origin
-// and unit direction; j: start offset in [0, 1).
-template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
-__device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& P, float ox,
-                                           float oy, float oz, float dx, float dy, float dz,
-                                           float j) {
-  RayResult res = {0.0f, 0.0f, 0.0f, 0.0f, 0u};
-  // slab test; an axis with d_k == 0 passes iff the origin lies in the slab
-  float tn = 0.0f, tf = 3.402823466e38f;
+// Entry and exit distances of the ray (o, d) through the volume's box (slab
+// test); an axis with d_k == 0 passes iff the origin lies in its slab. False
+// when the ray misses.
+__device__ __forceinline__ bool ray_box(const DevVolume& v, float ox, float oy, float oz, float dx,
+                                        float dy, float dz, float& tn, float& tf) {
+  tn = 0.0f;
+  tf = 3.402823466e38f;
   bool hit = true;
   const float o3[3] = {ox, oy, oz}, d3[3] = {dx, dy, dz};
 #pragma unroll
@@ -397,7 +435,26 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
       tf = fminf(tf, fmaxf(t0, t1));
     }
   }
-  if (!hit || !(tf > tn)) return res;
+  return hit && tf > tn;
+}
+
+struct RayResult {
+  float r, g, b, a;
+  // counted only on request: density lookups performed, primary samples
+  // taken (up to the early exit), and bit i set when sample i (i < 32) ran a
+  // light march
+  uint32_t lookups, primary, light_mask;
+};
+
+// One primary ray through the volume (Sections 1, 3.1, 3.2). (o, d): origin
+// and unit direction; j: start offset in [0, 1).
+template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+__device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& P, float ox,
+                                           float oy, float oz, float dx, float dy, float dz,
+                                           float j) {
+  RayResult res = {0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+  float tn, tf;
+  if (!ray_box(v, ox, oy, oz, dx, dy, dz, tn, tf)) return res;
 
   const float D = (tf - tn) / (float)P.steps;
   const float mu = dx * P.s[0] + dy * P.s[1] + dz * P.s[2];
@@ -408,7 +465,7 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
   const float xD = P.alpha * D;         // optical depth per unit density for one step
 
   float T = 1.0f, Sr = 0.0f, Sg = 0.0f, Sb = 0.0f;
-  uint32_t n = 0;
+  uint32_t n = 0, prim = 0, mask = 0;
 #if CLOUD_PREFETCH
   // The next sample's density is fetched before this sample's light march,
   // so its latency overlaps the light lookups (results are unchanged; a
@@ -431,12 +488,18 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
 #else
     const float rho = density<DT, LAYOUT, DETAIL>(v, px, py, pz);
 #endif
-    if constexpr (COUNT) n += 1;
+    if constexpr (COUNT) {
+      n += 1;
+      prim += 1;
+    }
     if (rho > 0.0f) {
       float TL = 1.0f;
       if (P.light_steps > 0) {
         TL = light_transmittance<DT, LAYOUT, DETAIL>(v, P, px, py, pz);
-        if constexpr (COUNT) n += (uint32_t)P.light_steps;
+        if constexpr (COUNT) {
+          n += (uint32_t)P.light_steps;
+          if (i < 32) mask |= 1u << i;
+        }
       }
       const float lr = fmaf(sr, TL, P.amb[0]), lg = fmaf(sg, TL, P.amb[1]),
                   lb = fmaf(sb, TL, P.amb[2]);
@@ -462,6 +525,8 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
   res.b = Sb;
   res.a = 1.0f - T;
   res.lookups = n;
+  res.primary = prim;
+  res.light_mask = mask;
   return res;
 }
 

@@ -11,14 +11,37 @@ namespace cloud {
 struct Tuning {
   int supertile = 4;   // render tile walk: S x S super-tiles (0 = row-major)
   int taa_tile = 32;   // resolve tile width in pixels (16, 32 or 64; 256 pixels a tile)
+  // cap on resident render workgroups per CU: 0 none, -1 automatic (3 for
+  // float32 packed volumes, whose two fetches per lookup thrash the caches
+  // when more rays are in flight; none otherwise)
+  int render_blocks_per_cu = -1;
 };
 Tuning& tuning();
 
-// Render n_views (<= kMaxViews) cameras into out [n_views][H][W][4]; with
-// counts != nullptr, add the density lookups to *counts instead (no image).
+// Dynamic LDS bytes that cap a 256-thread kernel using static_lds bytes of
+// LDS at blocks_per_cu resident workgroups per CU on the current device (0
+// when blocks_per_cu <= 0; -1 when the cap cannot be reached this way).
+long long residency_lds(int blocks_per_cu, size_t static_lds);
+
+// Resident workgroups per CU of the render kernel for this volume under the
+// current tuning (the ceiling kernel is run at the same residency).
+int render_residency(int dtype, int layout, bool detail);
+
+// Render n_views (<= kMaxViews) cameras into out [n_views][H][W][4]. With
+// counts or trace given, store no image: add the density lookups to *counts
+// and/or write each pixel's (primary samples, light-march mask) to trace
+// [n_views][H][W][2].
 hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevParams& p,
                          const DevCameras& c, int n_views, uint32_t frame, int W, int H,
-                         float* out, unsigned long long* counts, hipStream_t s);
+                         float* out, unsigned long long* counts, uint32_t* trace,
+                         hipStream_t s);
+
+// Fetch-only replay of a render's lookups (random == false: the positions
+// recorded in trace; random == true: as many lookups per pixel at uniformly
+// random footprints of the volume) into out [n_views][H][W][4].
+hipError_t launch_ceiling(const DevVolume& v, int dtype, int layout, const DevParams& p,
+                          const DevCameras& c, int n_views, uint32_t frame, int W, int H,
+                          const uint32_t* trace, bool random, float* out, hipStream_t s);
 
 // March n explicit rays into out [n][4].
 hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParams& p,

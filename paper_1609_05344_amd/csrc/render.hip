@@ -2,6 +2,8 @@
 // kernels, and their launchers.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "cloud_device.h"
 #include "cloud_launch.h"
 
@@ -16,8 +18,9 @@ Tuning& tuning() {
 // cloud_render / cloud_render_views / cloud_count_lookups: one thread per
 // pixel. A 256-thread workgroup covers a 16x16 pixel tile as four 8x8 wave
 // tiles, so the 64 rays of a wavefront are a compact bundle that samples
-// neighbouring texels. COUNT adds up the density lookups instead of storing
-// the image.
+// neighbouring texels. COUNT adds up the density lookups (into counts, if
+// given) and records each pixel's (primary samples, light-march mask) pair
+// (into trace, if given) instead of storing the image.
 // ---------------------------------------------------------------------------
 
 // Minimum waves per SIMD the register allocator must leave room for (0: the
@@ -36,7 +39,8 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
                                                      DevCameras cams, uint32_t frame, int W,
                                                      int H, int tiles_x, int tiles_y, int S,
                                                      float4* __restrict__ out,
-                                                     unsigned long long* __restrict__ counts) {
+                                                     unsigned long long* __restrict__ counts,
+                                                     uint2* __restrict__ trace) {
   const int tiles_per_view = tiles_x * tiles_y;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int view = tile / tiles_per_view;
@@ -49,7 +53,7 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
   stage_occupancy(vol);
   if (!COUNT && !inside) return;
 
-  RayResult r = {0.0f, 0.0f, 0.0f, 0.0f, 0u};
+  RayResult r = {0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
   if (inside) {
     const DevCamera& c = cams.c[view];
     float dx, dy, dz;
@@ -58,8 +62,11 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
     r = march<DT, LAYOUT, DETAIL, COUNT>(vol, prm, c.pos[0], c.pos[1], c.pos[2], dx, dy, dz, j);
   }
   if constexpr (COUNT) {
-    const uint32_t s = wave_sum(r.lookups);
-    if (lane == 0) atomicAdd(counts, (unsigned long long)s);
+    if (counts) {
+      const uint32_t s = wave_sum(r.lookups);
+      if (lane == 0) atomicAdd(counts, (unsigned long long)s);
+    }
+    if (trace && inside) trace[((size_t)view * H + py) * W + px] = make_uint2(r.primary, r.light_mask);
   } else {
     out[((size_t)view * H + py) * W + px] = make_float4(r.r, r.g, r.b, r.a);
   }
@@ -209,6 +216,75 @@ static hipError_t dispatch(int dtype, int layout, bool detail, bool count, F& f)
   }
 }
 
+// LDS bytes per CU and per workgroup of device dev (cached; false on error).
+static bool lds_limits(int dev, int* per_cu, int* per_block) {
+  constexpr int kDevs = 64;
+  static std::mutex mu;
+  static int cu[kDevs], blk[kDevs];
+  if (dev < 0 || dev >= kDevs) return false;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!cu[dev]) {
+    int a = 0, b = 0;
+    if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        a <= 0 || b <= 0)
+      return false;
+    cu[dev] = a;
+    blk[dev] = b;
+  }
+  *per_cu = cu[dev];
+  *per_block = blk[dev];
+  return true;
+}
+
+template <typename K>
+static size_t static_lds_of(K fn) {
+  hipFuncAttributes a;
+  return hipFuncGetAttributes(&a, reinterpret_cast<const void*>(fn)) == hipSuccess
+             ? a.sharedSizeBytes
+             : kOccupancyWords * 4;
+}
+
+long long residency_lds(int blocks_per_cu, size_t static_lds) {
+  if (blocks_per_cu <= 0) return 0;
+  int dev = 0, per_cu = 0, per_block = 0;
+  if (hipGetDevice(&dev) != hipSuccess || !lds_limits(dev, &per_cu, &per_block)) return -1;
+  // blocks_per_cu + 1 workgroups of (static + dynamic) bytes must not fit
+  long long total = (long long)per_cu / (blocks_per_cu + 1) + 1;
+  total = (total + 255) & ~255LL;
+  if ((long long)blocks_per_cu * total > per_cu || total > per_block) return -1;
+  return total > (long long)static_lds ? total - (long long)static_lds : 0;
+}
+
+// The residency cap in force for a render of this dtype and layout.
+template <int DT, int LAYOUT>
+static int render_cap() {
+  const int t = tuning().render_blocks_per_cu;
+  if (t >= 0) return t;
+  return DT == DT_F32 && LAYOUT != LAYOUT_DENSE ? 3 : 0;
+}
+
+template <int DT, int LAYOUT, bool DETAIL>
+static int residency_of() {
+  const void* fn = reinterpret_cast<const void*>(render_kernel<DT, LAYOUT, DETAIL, false>);
+  static const size_t slds = static_lds_of(render_kernel<DT, LAYOUT, DETAIL, false>);
+  const long long pad = residency_lds(render_cap<DT, LAYOUT>(), slds);
+  int n = 0;
+  if (pad < 0 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, (size_t)pad) != hipSuccess)
+    return 0;
+  return n;
+}
+
+struct ResidencyQuery {
+  template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+  hipError_t run() {
+    n = residency_of<DT, LAYOUT, DETAIL>();
+    return hipSuccess;
+  }
+  int n = 0;
+};
+
 struct RenderLaunch {
   const DevVolume& v;
   const DevParams& p;
@@ -218,15 +294,23 @@ struct RenderLaunch {
   int W, H;
   float* out;
   unsigned long long* counts;
+  uint32_t* trace;
   hipStream_t s;
   template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
   hipError_t run() {
     const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
     const int tiles_per_view = tiles_x * tiles_y;
     const int blocks = tiles_per_view * n_views;
-    hipLaunchKernelGGL((render_kernel<DT, LAYOUT, DETAIL, COUNT>), dim3(blocks), dim3(256), 0, s,
+    size_t lds = 0;
+    if (!COUNT && render_cap<DT, LAYOUT>() > 0) {
+      static const size_t slds = static_lds_of(render_kernel<DT, LAYOUT, DETAIL, COUNT>);
+      const long long pad = residency_lds(render_cap<DT, LAYOUT>(), slds);
+      if (pad < 0) return hipErrorInvalidValue;
+      lds = (size_t)pad;
+    }
+    hipLaunchKernelGGL((render_kernel<DT, LAYOUT, DETAIL, COUNT>), dim3(blocks), dim3(256), lds, s,
                        v, p, c, frame, W, H, tiles_x, tiles_y, tuning().supertile,
-                       reinterpret_cast<float4*>(out), counts);
+                       reinterpret_cast<float4*>(out), counts, reinterpret_cast<uint2*>(trace));
     return hipGetLastError();
   }
 };
@@ -251,9 +335,16 @@ struct RaysLaunch {
 
 hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevParams& p,
                          const DevCameras& c, int n_views, uint32_t frame, int W, int H,
-                         float* out, unsigned long long* counts, hipStream_t s) {
-  RenderLaunch f{v, p, c, n_views, frame, W, H, out, counts, s};
-  return dispatch(dtype, layout, v.detail != nullptr, counts != nullptr, f);
+                         float* out, unsigned long long* counts, uint32_t* trace,
+                         hipStream_t s) {
+  RenderLaunch f{v, p, c, n_views, frame, W, H, out, counts, trace, s};
+  return dispatch(dtype, layout, v.detail != nullptr, counts != nullptr || trace != nullptr, f);
+}
+
+int render_residency(int dtype, int layout, bool detail) {
+  ResidencyQuery q;
+  dispatch(dtype, layout, detail, false, q);
+  return q.n;
 }
 
 hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParams& p,

@@ -44,9 +44,10 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "cloud.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(cloud_volume),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cloud_volume),"
         " sizeof(cloud_camera), sizeof(cloud_params), offsetof(cloud_volume, layout),"
-        " offsetof(cloud_params, t_eps), offsetof(cloud_volume, detail));return 0;}\n")
+        " offsetof(cloud_params, t_eps), offsetof(cloud_volume, detail),"
+        " sizeof(cloud_serve_config), offsetof(cloud_serve_config, queues));return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True)
@@ -54,7 +55,8 @@ def test_struct_layout_matches_header(tmp_path):
                                           check=True).stdout.split()]
     assert got == [ctypes.sizeof(_lib.cloud_volume), ctypes.sizeof(_lib.cloud_camera),
                    ctypes.sizeof(_lib.cloud_params), _lib.cloud_volume.layout.offset,
-                   _lib.cloud_params.t_eps.offset, _lib.cloud_volume.detail.offset]
+                   _lib.cloud_params.t_eps.offset, _lib.cloud_volume.detail.offset,
+                   ctypes.sizeof(_lib.cloud_serve_config), _lib.cloud_serve_config.queues.offset]
 
 
 def test_argument_errors_before_any_launch(lib):

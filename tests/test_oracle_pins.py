@@ -473,3 +473,51 @@ def test_mirror_symmetry():
     img = O.render(vol, cam, p, 32, 20)
     assert np.max(np.abs(img - img[:, ::-1])) < 1e-12
     assert img[..., 3].max() > 0.1
+
+
+# ---------------------------------------------------------------------------
+# Lookup trace (which lookups the march performs): against the sample points
+# and the early-exit closed form
+# ---------------------------------------------------------------------------
+
+def test_trace_light_mask_is_density_positive_at_the_sample_points():
+    rho = scenes.make_density(scenes.WORKLOADS["C1"].volume, cache=False)
+    vol = O.OracleVolume(base=rho)
+    cam = scenes.orbit_camera(2.0, 210.0, 20.0)
+    p = params(steps=12, jitter=1, t_eps=0.0)
+    W, H = 24, 18
+    gx, gy = np.meshgrid(np.arange(W), np.arange(H), indexing="xy")
+    px, py = gx.reshape(-1), gy.reshape(-1)
+    _, lk, (prim, mask) = O.render(vol, cam, p, W, H, frame=3, pixels=np.stack([px, py], 1),
+                                   return_lookups=True, return_trace=True)
+    o, d = O.camera_rays(cam, W, H, px, py)
+    tn, tf, hit = O.ray_box(o, d, vol.box_min, vol.box_max)
+    j = O.jitter_offset(px, py, 3, p.seed)
+    # no early exit: every ray through the box takes all N samples
+    assert np.array_equal(prim, np.where(hit, p.steps, 0))
+    want = np.zeros(px.size, dtype=np.uint64)
+    for i in range(p.steps):
+        t = tn + (i + j) * (tf - tn) / p.steps
+        r = O.density(vol, o + t[:, None] * d)
+        want |= np.where(hit & (r > 0), np.uint64(1) << np.uint64(i), np.uint64(0))
+    assert np.array_equal(mask, want)
+    bits = np.array([bin(int(m)).count("1") for m in mask])
+    assert lk == int(prim.sum()) + p.light_steps * int(bits.sum())
+    assert 0 < bits.sum() < hit.sum() * p.steps
+
+
+@pytest.mark.parametrize("alpha,eps", [(10.0, 1e-2), (40.0, 1e-5), (3.0, 1e-5)])
+def test_trace_early_exit_closed_form(alpha, eps):
+    # homogeneous unit density: T after k samples is exp(-alpha D k), so the
+    # march stops after the first k with T < eps (at most N samples)
+    vol = const_volume(1.0)
+    p = params(steps=16, alpha=alpha, t_eps=eps, light_steps=0)
+    o = np.array([[0.0, 0.0, -3.0]])
+    d = np.array([[0.0, 0.0, 1.0]])
+    _, (prim, mask) = O.march_rays(vol, o, d, p, return_trace=True)
+    D = 1.0 / p.steps
+    k = np.arange(1, p.steps + 1)
+    below = np.nonzero(np.exp(-alpha * D * k) < eps)[0]
+    want = int(k[below[0]]) if below.size else p.steps
+    assert int(prim[0]) == want
+    assert int(mask[0]) == 0      # no light march with light_steps = 0

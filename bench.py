@@ -33,6 +33,9 @@ KERNEL_SOURCES = ["cloud_device.h", "cloud_types.h", "render.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
 
 
+JITTER_NAMES = {0: "none (j = 1/2)", 1: "per-pixel", 2: "per 8x8 tile", 3: "per frame"}
+
+
 def kernel_source_sha1() -> str:
     """Hash of the sources the render kernel is built from: a recorded counter
     measurement applies only while this hash is unchanged."""
@@ -304,22 +307,26 @@ def quality_report(cf, scenes, torch) -> dict:
     cam = w2.camera(0)
     from dataclasses import replace
     ref = cf.cloud_render(vol, cam, replace(w2.params, steps=128, jitter=0), 0, W, H).cpu().numpy()
-    hist = torch.zeros((H, W, 4), device="cuda")
     cur = torch.empty((H, W, 4), device="cuda")
-    for f in range(16):
-        cf.cloud_render(vol, cam, w2.params, f, W, H, out=cur)
-        cf.cloud_taa_resolve(cur, hist, hist, w2.taa_blend, f)
-    taa = hist.cpu().numpy()
-    one = cf.cloud_render(vol, cam, w2.params, 15, W, H).cpu().numpy()
-    flat = cf.cloud_render(vol, cam, replace(w2.params, jitter=0), 15, W, H).cpu().numpy()
+
+    def accumulated(mode):
+        hist = torch.zeros((H, W, 4), device="cuda")
+        for f in range(16):
+            cf.cloud_render(vol, cam, replace(w2.params, jitter=mode), f, W, H, out=cur)
+            cf.cloud_taa_resolve(cur, hist, hist, w2.taa_blend, f)
+        return hist.cpu().numpy()
 
     def err(a):
         d = np.abs(a.astype(np.float64) - ref)
         return {"mean_abs": float(d.mean()), "p99_abs": float(np.percentile(d, 99)),
                 "max_abs": float(d.max())}
 
-    out["steps8_vs_128_C2"] = {"jitter_taa_16_frames": err(taa), "jitter_one_frame": err(one),
-                              "no_jitter": err(flat)}
+    one = cf.cloud_render(vol, cam, w2.params, 15, W, H).cpu().numpy()
+    flat = cf.cloud_render(vol, cam, replace(w2.params, jitter=0), 15, W, H).cpu().numpy()
+    out["steps8_vs_128_C2"] = {"jitter_taa_16_frames": err(accumulated(1)),
+                              "jitter_one_frame": err(one), "no_jitter": err(flat),
+                              "tile_jitter_taa_16_frames": err(accumulated(2)),
+                              "frame_jitter_taa_16_frames": err(accumulated(3))}
     return out
 
 
@@ -340,6 +347,9 @@ def main():
     ap.add_argument("--served-dtype", default="f16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--served-layout", default="oct", choices=["dense", "quad", "oct"])
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--jitter-mode", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="start offsets: 0 none, 1 per pixel (the workload's), 2 per 8x8 tile, "
+                         "3 per frame")
     ap.add_argument("--no-ceiling", action="store_true",
                     help="skip the gather-ceiling measurement")
     ap.add_argument("--serve-queues", type=int, default=1, choices=[1, 2])
@@ -386,7 +396,7 @@ def main():
         return
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.jitter_mode is None:
         cores = min(os.cpu_count() or 1, 16)
         cpu = cpu_baseline(args.workload, args.dtype, args.cpu_frames, cores)
 
@@ -402,6 +412,9 @@ def main():
     sc = scenes.make_scene(w, dtype=args.dtype)
     vol = cf.device_volume(sc, dev, layout=args.layout, occupancy=not args.no_occupancy)
     W, H, p = w.width, w.height, w.params
+    if args.jitter_mode is not None:
+        from dataclasses import replace
+        p = replace(p, jitter=args.jitter_mode)
     total = args.warmup + args.steps
 
     if args.calibrate_copy_mib:
@@ -473,7 +486,7 @@ def main():
         "data": "synthetic: seeded 5-octave value-noise FBM density 256^3 "
                 f"({args.dtype} storage, {args.layout} layout), orbiting camera",
         "config": {"workload": f"{w.name}: {w.description}", "width": W, "height": H,
-                   "primary_steps": p.steps, "light_steps": p.light_steps, "jitter": "per-pixel",
+                   "primary_steps": p.steps, "light_steps": p.light_steps, "jitter": JITTER_NAMES[p.jitter],
                    "integration": "analytic", "taa_blend": w.taa_blend,
                    "volume": f"{w.volume.n}^3 {args.dtype}", "layout": args.layout,
                    "occupancy_skip": not args.no_occupancy,

@@ -131,7 +131,11 @@ typedef struct {
  *  ambient      ambient light added to the incident light (Section 1).
  *  jitter       0: j = 0.5 for every ray; 1: per-pixel offset j in [0, 1)
  *               from the PCG hash chain of (px, py, frame_index, seed)
- *               (Section 3.2's random per-pixel start offset).
+ *               (Section 3.2's random per-pixel start offset); 2: one offset
+ *               per 8x8-pixel tile, the chain of (px >> 3, py >> 3, ...);
+ *               3: one offset per frame, the chain of (0, 0, ...). Modes 2
+ *               and 3 are coherent variants (the cache-friendlier jitter
+ *               Section 5 leaves to future work).
  *  integration  1: analytic, S += T L_in (1 - exp(-rho alpha D)) (Section 3.1);
  *               0: the basic rule, T updated first, S += T rho alpha D L_in.
  *  t_eps        stop a ray once T < t_eps ("until the alpha reaches 1",
@@ -178,8 +182,9 @@ int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras,
  * rays against closed forms).
  *  origins, dirs  device [n][3] float32; dirs are normalised by the library
  *                 and must be non-zero.
- *  pixel_xy       device [n][2] uint32 (px, py) fed to the jitter hash, or
- *                 NULL for j = 0.5; ignored when params->jitter == 0.
+ *  pixel_xy       device [n][2] uint32 (px, py) fed to the jitter hash
+ *                 (under params->jitter's mode), or NULL for j = 0.5;
+ *                 ignored when params->jitter == 0.
  *  out_rgba       device [n][4] float32. n == 0 is a no-op. */
 int cloud_march_rays(const cloud_volume* volume, const float* origins,
                      const float* dirs, const uint32_t* pixel_xy, int64_t n,

@@ -82,6 +82,33 @@ def jitter_offset(px, py, frame: int, seed: int):
     return (h >> 8) * 2.0 ** -24
 
 
+JITTER_NONE, JITTER_PIXEL, JITTER_TILE, JITTER_FRAME = 0, 1, 2, 3
+
+
+def jitter_for(mode: int, px, py, frame: int, seed: int):
+    """Start offsets of pixels (px, py) under a jitter mode (reading R17).
+
+    0: none (None: the march uses j = 0.5); 1: per pixel (Section 3.2), the
+    hash of (px, py); 2: one offset per 8x8-pixel tile, the hash of
+    (px >> 3, py >> 3); 3: one offset per frame, the hash of (0, 0). Modes 2
+    and 3 are the coherent variants the paper's Section 5 points to."""
+    mode = int(mode)
+    if mode == JITTER_NONE:
+        return None
+    if mode not in (JITTER_PIXEL, JITTER_TILE, JITTER_FRAME):
+        raise ValueError(f"unknown jitter mode {mode}")
+    if np.ndim(px) == 0 and np.ndim(py) == 0:
+        px, py = int(px), int(py)
+    else:
+        px = np.asarray(px, dtype=np.int64)
+        py = np.asarray(py, dtype=np.int64)
+    if mode == JITTER_TILE:
+        px, py = px >> 3, py >> 3
+    elif mode == JITTER_FRAME:
+        px, py = px * 0, py * 0
+    return jitter_offset(px, py, frame, seed)
+
+
 # ---------------------------------------------------------------------------
 # Phase function (Section 1, Henyey-Greenstein; reading R8)
 # ---------------------------------------------------------------------------
@@ -322,7 +349,7 @@ def render(vol: OracleVolume, cam, params, width: int, height: int, frame: int =
         pixels = np.asarray(pixels, dtype=np.int64).reshape(-1, 2)
         px, py = pixels[:, 0], pixels[:, 1]
     o, d = camera_rays(cam, width, height, px, py)
-    j = jitter_offset(px, py, frame, int(params.seed)) if int(params.jitter) else None
+    j = jitter_for(int(params.jitter), px, py, frame, int(params.seed))
     out = march_rays(vol, o, d, params, jitter=j, return_lookups=return_lookups,
                      return_trace=return_trace)
     if not (return_lookups or return_trace):

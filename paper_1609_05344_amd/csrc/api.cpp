@@ -198,7 +198,7 @@ int prepare_params(const cloud_params* p, const cloud_volume* v, DevParams* out)
                               (double)p->sun_dir[1] * p->sun_dir[1] +
                               (double)p->sun_dir[2] * p->sun_dir[2]);
   if (!(sl > 0.0)) return fail(CLOUD_E_INVALID, "sun_dir must be non-zero");
-  if (p->jitter != 0 && p->jitter != 1) return fail(CLOUD_E_INVALID, "jitter must be 0 or 1");
+  if (p->jitter < 0 || p->jitter > 3) return fail(CLOUD_E_INVALID, "jitter must be 0, 1, 2 or 3");
   if (p->integration != 0 && p->integration != 1)
     return fail(CLOUD_E_INVALID, "integration must be 0 (naive) or 1 (analytic)");
   if (!std::isfinite(p->t_eps) || p->t_eps < 0.0f) return fail(CLOUD_E_INVALID, "t_eps must be finite and >= 0");

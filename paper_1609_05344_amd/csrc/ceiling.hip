@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void gather_ceiling_kernel(DevVolume vol, DevP
     const DevCamera& c = cams.c[view];
     float dx, dy, dz;
     camera_dir(c, px, py, W, H, dx, dy, dz);
-    const float j = prm.jitter ? jitter_offset((uint32_t)px, (uint32_t)py, frame, prm.seed) : 0.5f;
+    const float j = jitter_for(prm.jitter, (uint32_t)px, (uint32_t)py, frame, prm.seed);
     const float ox = c.pos[0], oy = c.pos[1], oz = c.pos[2];
     float tn, tf;
     if (n_prim > 0 && ray_box(vol, ox, oy, oz, dx, dy, dz, tn, tf)) {

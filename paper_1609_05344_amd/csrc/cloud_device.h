@@ -52,6 +52,23 @@ __device__ __forceinline__ float jitter_offset(uint32_t px, uint32_t py, uint32_
   return (float)(h >> 8) * 5.9604644775390625e-8f;
 }
 
+// Start offset of pixel (px, py) under jitter mode m: 0 none (j = 1/2); 1 per
+// pixel; 2 one offset per 8x8-pixel tile (one per wavefront); 3 one offset
+// per frame. Modes 2 and 3 hash (px >> 3, py >> 3) and (0, 0) instead of
+// (px, py).
+__device__ __forceinline__ float jitter_for(int m, uint32_t px, uint32_t py, uint32_t frame,
+                                            uint32_t seed) {
+  if (m == 0) return 0.5f;
+  if (m == 2) {
+    px >>= 3;
+    py >>= 3;
+  } else if (m == 3) {
+    px = 0u;
+    py = 0u;
+  }
+  return jitter_offset(px, py, frame, seed);
+}
+
 // ---------------------------------------------------------------------------
 // Texel decoding
 // ---------------------------------------------------------------------------

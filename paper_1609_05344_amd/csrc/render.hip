@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
     const DevCamera& c = cams.c[view];
     float dx, dy, dz;
     camera_dir(c, px, py, W, H, dx, dy, dz);
-    const float j = prm.jitter ? jitter_offset((uint32_t)px, (uint32_t)py, frame, prm.seed) : 0.5f;
+    const float j = jitter_for(prm.jitter, (uint32_t)px, (uint32_t)py, frame, prm.seed);
     r = march<DT, LAYOUT, DETAIL, COUNT>(vol, prm, c.pos[0], c.pos[1], c.pos[2], dx, dy, dz, j);
   }
   if constexpr (COUNT) {
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void rays_kernel(DevVolume vol, DevParams prm,
   dy *= inv;
   dz *= inv;
   float j = 0.5f;
-  if (prm.jitter && pixel_xy) j = jitter_offset(pixel_xy[2 * i], pixel_xy[2 * i + 1], frame, prm.seed);
+  if (pixel_xy) j = jitter_for(prm.jitter, pixel_xy[2 * i], pixel_xy[2 * i + 1], frame, prm.seed);
   const RayResult r = march<DT, LAYOUT, DETAIL, false>(vol, prm, ox, oy, oz, dx, dy, dz, j);
   out[i] = make_float4(r.r, r.g, r.b, r.a);
 }

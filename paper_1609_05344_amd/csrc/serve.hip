@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol, ServeT
       float dx, dy, dz;
       camera_dir(it.cam, px, py, it.width, it.height, dx, dy, dz);
       const float j =
-          it.prm.jitter ? jitter_offset((uint32_t)px, (uint32_t)py, it.frame, it.prm.seed) : 0.5f;
+          jitter_for(it.prm.jitter, (uint32_t)px, (uint32_t)py, it.frame, it.prm.seed);
       const RayResult r = march<DT, LAYOUT, DETAIL, false>(vol, it.prm, it.cam.pos[0],
                                                            it.cam.pos[1], it.cam.pos[2], dx, dy,
                                                            dz, j);

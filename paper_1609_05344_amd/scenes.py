@@ -248,7 +248,7 @@ class Params:
     sun_dir: tuple = SUN_DIR
     sun_color: tuple = SUN_COLOR
     ambient: tuple = AMBIENT
-    jitter: int = 1             # 0: fixed offset 0.5; 1: per-pixel hash
+    jitter: int = 1             # 0: fixed 0.5; 1: per pixel; 2: per 8x8 tile; 3: per frame
     seed: int = JITTER_SEED
     integration: int = 1        # 0: naive S = T L; 1: analytic
     t_eps: float = 1e-5         # early-out threshold on transmittance (0 = off)

@@ -171,7 +171,7 @@ def test_gpu_telescoping_on_noise(cf, torch):
 # full frames and sampled pixels against the oracle
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("integ,jit", [(1, 0), (0, 0), (1, 1), (0, 1)])
+@pytest.mark.parametrize("integ,jit", [(1, 0), (0, 0), (1, 1), (0, 1), (1, 2), (1, 3), (0, 2)])
 def test_c1_full_frame(cf, torch, integ, jit):
     say(f"C1 64x64 full frame integ={integ} jitter={jit}")
     w = scenes.workload("C1")
@@ -210,6 +210,25 @@ def test_full_size_sampled(cf, torch, name, frame):
     want_e = O.render(oracle_volume(sc), w.camera(frame), w.params, w.width, w.height, frame=frame,
                       pixels=edge)
     assert max_err(got[edge[:, 1], edge[:, 0]], want_e) < FP32_TOL
+
+
+@pytest.mark.parametrize("jit", [2, 3])
+def test_coherent_jitter_sampled_and_structured(cf, torch, jit):
+    w = scenes.workload("H")
+    say(f"H 1080p jitter mode {jit}: sampled parity, explicit rays")
+    sc = scenes.make_scene(w)
+    p = replace(w.params, jitter=jit)
+    vol = cf.device_volume(sc, layout="quad", occupancy=True)
+    got = to_np(cf.cloud_render(vol, w.camera(4), p, 4, w.width, w.height))
+    pix = scenes.random_pixels(w.width, w.height, 2000, seed=41 + jit)
+    want = O.render(oracle_volume(sc), w.camera(4), p, w.width, w.height, frame=4, pixels=pix)
+    assert max_err(got[pix[:, 1], pix[:, 0]], want) < FP32_TOL
+    # explicit rays with pixel coordinates take the same mode
+    o, d = O.camera_rays(w.camera(4), w.width, w.height, pix[:, 0], pix[:, 1])
+    dev = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    rays = to_np(cf.cloud_march_rays(vol, dev(o, torch.float32), dev(d, torch.float32),
+                                     dev(pix.astype(np.int32), torch.int32), p, 4))
+    assert max_err(rays, want) < FP32_TOL
 
 
 def test_views_match_single_renders(cf, torch):

@@ -521,3 +521,46 @@ def test_trace_early_exit_closed_form(alpha, eps):
     want = int(k[below[0]]) if below.size else p.steps
     assert int(prim[0]) == want
     assert int(mask[0]) == 0      # no light march with light_steps = 0
+
+
+# ---------------------------------------------------------------------------
+# Coherent jitter variants (reading R17): structure, and the same unbiased
+# step average over frames as the per-pixel offset
+# ---------------------------------------------------------------------------
+
+def test_jitter_modes_structure():
+    py, px = np.meshgrid(np.arange(40), np.arange(48), indexing="ij")
+    px, py = px.reshape(-1), py.reshape(-1)
+    assert O.jitter_for(0, px, py, 3, 1609) is None
+    assert np.array_equal(O.jitter_for(1, px, py, 3, 1609), O.jitter_offset(px, py, 3, 1609))
+    tile = O.jitter_for(2, px, py, 3, 1609)
+    key = (py // 8) * 6 + px // 8
+    for k in np.unique(key):
+        vals = tile[key == k]
+        assert np.all(vals == vals[0])
+        assert vals[0] == O.jitter_offset(int(px[key == k][0]) // 8, int(py[key == k][0]) // 8, 3, 1609)
+    assert np.unique(tile).size == np.unique(key).size     # 30 tiles, 30 distinct offsets
+    frame = O.jitter_for(3, px, py, 3, 1609)
+    assert np.all(frame == O.jitter_offset(0, 0, 3, 1609))
+    assert O.jitter_for(3, px[:1], py[:1], 4, 1609)[0] != frame[0]
+    with pytest.raises(ValueError):
+        O.jitter_for(4, px, py, 0, 1)
+
+
+def test_frame_jitter_mean_over_frames_matches_closed_form():
+    # one offset per frame: over many frames the offsets are uniform, so the
+    # mean of a ray's colour is the same closed form as the per-pixel mean
+    c, alpha, H, N = 1.0, 10.0, 1.0, 8
+    sig = c * alpha
+    x = sig * H / N
+    frames = np.arange(4096)
+    j = np.array([O.jitter_for(3, 5, 7, int(f), 1609) for f in frames])
+    n = j.size
+    p = params(steps=N, alpha=alpha, sun_dir=(0.0, 1.0, 0.0), sun_color=(4.0, 0.0, 0.0),
+               ambient=(0.0, 0.0, 0.0), jitter=3)
+    rgba = O.march_rays(const_volume(c), np.tile([0.0, 2.0, 0.0], (n, 1)),
+                        np.tile([0.0, -1.0, 0.0], (n, 1)), p, jitter=j)
+    P = O.hg_phase(-1.0, 0.6)
+    expect = 4.0 * P * (-math.expm1(-2 * sig * H)) * math.tanh(x / 2) / x
+    se = rgba[:, 0].std() / math.sqrt(n)
+    assert abs(rgba[:, 0].mean() - expect) < 4 * se

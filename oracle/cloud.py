@@ -265,8 +265,12 @@ def light_transmittance(vol: OracleVolume, p, s_hat, light_steps: int, alpha: fl
 # The march (Sections 1 and 3)
 # ---------------------------------------------------------------------------
 
+DEPTH_ALPHA_MIN = 0.01
+
+
 def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
-               return_lookups: bool = False, return_trace: bool = False):
+               return_lookups: bool = False, return_trace: bool = False,
+               return_depth: bool = False):
     """March n rays; returns RGBA [n,4] (premultiplied colour, alpha = 1 - T).
 
     origins, dirs: [n,3] (dirs need not be unit length; they are normalised).
@@ -275,7 +279,11 @@ def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
             integration (0 naive, 1 analytic), t_eps.
     return_lookups adds the number of density lookups performed; return_trace
     adds, per ray, the primary samples taken and a mask with bit i set when
-    sample i ran the light march.
+    sample i ran the light march; return_depth adds each ray's representative
+    depth (reading R18): the mean sample distance t_i weighted by the opacity
+    each step adds, T_before - T_after, when alpha >= DEPTH_ALPHA_MIN; the
+    middle of the ray's chord through the box below that; 0 (at infinity)
+    for rays that miss the box.
     Each primary step (Section 1): sample rho, march towards the sun for the
     incident light, add the ambient term, integrate over the step (Section
     3.1), update T, stop once T < t_eps (R12)."""
@@ -299,6 +307,7 @@ def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
     lookups = 0
     prim = np.zeros(n, dtype=np.int64)
     mask = np.zeros(n, dtype=np.uint64)
+    opacity_t = np.zeros(n)
     for i in range(N):
         idx = np.nonzero(alive)[0]
         if idx.size == 0:
@@ -317,6 +326,7 @@ def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
                 mask[idx[lit]] |= np.uint64(1) << np.uint64(i)
         L_in = c_sun[None, :] * (phase[idx] * TL)[:, None] + c_amb[None, :]
         x = rho * alpha * D[idx]
+        T_before = T[idx].copy()
         if int(params.integration) == 1:
             # Section 3.1: S += T0 * L_in * (1 - e^{-x}) (R1, R2), then T update.
             S[idx] += (T[idx] * -np.expm1(-x))[:, None] * L_in
@@ -325,23 +335,31 @@ def march_rays(vol: OracleVolume, origins, dirs, params, jitter=None,
             # Section 3.1, basic approach: update T first, then use it (R3).
             T[idx] = T[idx] * np.exp(-x)
             S[idx] += (T[idx] * x)[:, None] * L_in
+        opacity_t[idx] += (T_before - T[idx]) * t
         eps = float(params.t_eps)
         if eps > 0.0:
             alive[idx] = T[idx] >= eps
     rgba = np.concatenate([S, (1.0 - T)[:, None]], axis=1)
     rgba[~hit] = 0.0
     extra = ([lookups] if return_lookups else []) + ([(prim, mask)] if return_trace else [])
+    if return_depth:
+        a = 1.0 - T
+        with np.errstate(divide="ignore", invalid="ignore"):
+            depth = np.where(a >= DEPTH_ALPHA_MIN, opacity_t / a, 0.5 * (tn + tf))
+        extra.append(np.where(hit, depth, 0.0))
     return (rgba, *extra) if extra else rgba
 
 
 def render(vol: OracleVolume, cam, params, width: int, height: int, frame: int = 0,
-           pixels=None, return_lookups: bool = False, return_trace: bool = False):
+           pixels=None, return_lookups: bool = False, return_trace: bool = False,
+           return_depth: bool = False):
     """Render the cloud layer (RGBA premultiplied, no background; R15).
 
     pixels: None for the whole image ([height, width, 4] result), or an
     [n,2] array of (px, py) for those pixels only ([n,4] result).
-    return_lookups / return_trace: as in march_rays (the trace per pixel, in
-    the result's pixel order)."""
+    return_lookups / return_trace / return_depth: as in march_rays (per-pixel
+    results in the result's pixel order; the depth as [height, width] for a
+    whole image)."""
     if pixels is None:
         py, px = np.meshgrid(np.arange(height), np.arange(width), indexing="ij")
         px, py = px.reshape(-1), py.reshape(-1)
@@ -351,13 +369,15 @@ def render(vol: OracleVolume, cam, params, width: int, height: int, frame: int =
     o, d = camera_rays(cam, width, height, px, py)
     j = jitter_for(int(params.jitter), px, py, frame, int(params.seed))
     out = march_rays(vol, o, d, params, jitter=j, return_lookups=return_lookups,
-                     return_trace=return_trace)
-    if not (return_lookups or return_trace):
+                     return_trace=return_trace, return_depth=return_depth)
+    if not (return_lookups or return_trace or return_depth):
         out = (out,)
-    rgba = out[0]
+    out = list(out)
     if pixels is None:
-        rgba = rgba.reshape(height, width, 4)
-    return (rgba, *out[1:]) if len(out) > 1 else rgba
+        out[0] = out[0].reshape(height, width, 4)
+        if return_depth:
+            out[-1] = out[-1].reshape(height, width)
+    return tuple(out) if len(out) > 1 else out[0]
 
 
 # ---------------------------------------------------------------------------
@@ -480,3 +500,63 @@ def taa_resolve(cur, hist, blend: float, frame_index: int):
     lo, hi = nb.min(axis=0), nb.max(axis=0)
     h = np.minimum(np.maximum(hist, lo), hi)
     return h + blend * (cur - h)
+
+
+def camera_project(cam, width: int, height: int, v):
+    """Continuous pixel coordinates (u, w) of directions v [n,3] (camera-space
+    vectors from the camera's position) for the pinhole of camera_rays: pixel
+    (px, py)'s centre direction maps to (px, py). Also returns z = v . forward
+    (the point is behind the camera when z <= 0)."""
+    pos = np.asarray(cam.pos, dtype=np.float64)
+    f = _normalize(np.asarray(cam.target, dtype=np.float64) - pos)
+    r = _normalize(np.cross(f, np.asarray(cam.up, dtype=np.float64)))
+    u = np.cross(r, f)
+    tan_half = math.tan(math.radians(cam.vfov_deg) * 0.5)
+    z = v @ f
+    with np.errstate(divide="ignore", invalid="ignore"):
+        x = (v @ r) / z
+        y = (v @ u) / z
+    uc = (x / (tan_half * (width / height)) + 1.0) * (width * 0.5) - 0.5
+    wc = (1.0 - y / tan_half) * (height * 0.5) - 0.5
+    return uc, wc, z
+
+
+def taa_resolve_reproject(cur, hist, depth, cam, prev_cam, blend: float, frame_index: int):
+    """Temporal resolve with camera reprojection (Section 3.2 names Playdead's
+    TAA, whose history is reprojected; reading R18). For each pixel, the point
+    at its representative depth along its ray (at infinity for depth 0) is
+    projected into the previous camera; the history is sampled there
+    bilinearly with edge clamping, then clamped into the current 3x3
+    neighbourhood min/max and blended, out = h + blend * (cur - h). A point
+    behind the previous camera or outside its image uses the current value
+    as history. Frame 0, or no history, copies cur."""
+    cur = np.asarray(cur, dtype=np.float64)
+    if hist is None or int(frame_index) == 0:
+        return cur.copy()
+    hist = np.asarray(hist, dtype=np.float64)
+    H, W = cur.shape[:2]
+    py, px = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    o, d = camera_rays(cam, W, H, px.reshape(-1), py.reshape(-1))
+    dep = np.asarray(depth, dtype=np.float64).reshape(-1)
+    prev_pos = np.asarray(prev_cam.pos, dtype=np.float64)
+    v = np.where((dep > 0.0)[:, None], o + dep[:, None] * d - prev_pos[None, :], d)
+    uc, wc, z = camera_project(prev_cam, W, H, v)
+    valid = (z > 0.0) & (uc >= -0.5) & (uc <= W - 0.5) & (wc >= -0.5) & (wc <= H - 0.5)
+    uc = np.where(valid, uc, 0.0)
+    wc = np.where(valid, wc, 0.0)
+    x0f, y0f = np.floor(uc), np.floor(wc)
+    fx, fy = (uc - x0f)[:, None], (wc - y0f)[:, None]
+    x0 = np.clip(x0f.astype(np.int64), 0, W - 1)
+    x1 = np.clip(x0f.astype(np.int64) + 1, 0, W - 1)
+    y0 = np.clip(y0f.astype(np.int64), 0, H - 1)
+    y1 = np.clip(y0f.astype(np.int64) + 1, 0, H - 1)
+    top = _lerp(hist[y0, x0], hist[y0, x1], fx)
+    bot = _lerp(hist[y1, x0], hist[y1, x1], fx)
+    h = _lerp(top, bot, fy)
+    c = cur.reshape(-1, 4)
+    h = np.where(valid[:, None], h, c)
+    pad = np.pad(cur, ((1, 1), (1, 1), (0, 0)), mode="edge")
+    nb = np.stack([pad[dy:dy + H, dx:dx + W] for dy in range(3) for dx in range(3)])
+    lo, hi = nb.min(axis=0).reshape(-1, 4), nb.max(axis=0).reshape(-1, 4)
+    h = np.minimum(np.maximum(h, lo), hi)
+    return (h + blend * (c - h)).reshape(H, W, 4)

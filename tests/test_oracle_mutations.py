@@ -47,6 +47,15 @@ PINS = {
     "early": lambda: P.test_early_out_bound(),
     "taa": lambda: (P.test_taa_brute_force_and_frame0(), P.test_taa_ema_closed_form_and_bounds()),
     "mirror": lambda: P.test_mirror_symmetry(),
+    "trace": lambda: (P.test_trace_light_mask_is_density_positive_at_the_sample_points(),
+                      [P.test_trace_early_exit_closed_form(a, e)
+                       for a, e in ((10.0, 1e-2), (40.0, 1e-5))]),
+    "jitter_modes": lambda: (P.test_jitter_modes_structure(),
+                             P.test_frame_jitter_mean_over_frames_matches_closed_form()),
+    "depth": lambda: (P.test_depth_homogeneous_slab_matches_continuous_mean(),
+                      P.test_depth_low_alpha_and_misses()),
+    "reproject": lambda: (P.test_reproject_with_a_still_camera_is_the_plain_resolve(),
+                          P.test_reproject_sideways_translation_samples_the_parallax_shift()),
 }
 
 MUTATIONS = [
@@ -108,6 +117,26 @@ MUTATIONS = [
      "return h + blend * (cur - h)", "return cur + blend * (h - cur)"),
     ("resolve without the clamp", "taa_resolve",
      "h = np.minimum(np.maximum(hist, lo), hi)", "h = hist"),
+    ("trace records the light march one sample late", "march_rays",
+     "mask[idx[lit]] |= np.uint64(1) << np.uint64(i)", "mask[idx[lit]] |= np.uint64(1) << np.uint64(i + 1)"),
+    ("tile jitter over 4x4 tiles", "jitter_for",
+     "px, py = px >> 3, py >> 3", "px, py = px >> 2, py >> 2"),
+    ("depth at the step start", "march_rays",
+     "opacity_t[idx] += (T_before - T[idx]) * t", "opacity_t[idx] += (T_before - T[idx]) * (t - j[idx] * D[idx])"),
+    ("depth weighted by transmittance", "march_rays",
+     "opacity_t[idx] += (T_before - T[idx]) * t", "opacity_t[idx] += T[idx] * t"),
+    ("depth of thin rays at the near plane", "march_rays",
+     "depth = np.where(a >= DEPTH_ALPHA_MIN, opacity_t / a, 0.5 * (tn + tf))",
+     "depth = np.where(a >= DEPTH_ALPHA_MIN, opacity_t / a, tn)"),
+    ("reprojection from the current camera", "taa_resolve_reproject",
+     "o + dep[:, None] * d - prev_pos[None, :]", "dep[:, None] * d"),
+    ("reprojection without the half-pixel shift", "camera_project",
+     "uc = (x / (tan_half * (width / height)) + 1.0) * (width * 0.5) - 0.5",
+     "uc = (x / (tan_half * (width / height)) + 1.0) * (width * 0.5)"),
+    ("bilinear weights swapped", "taa_resolve_reproject",
+     "top = _lerp(hist[y0, x0], hist[y0, x1], fx)", "top = _lerp(hist[y0, x0], hist[y0, x1], fy)"),
+    ("reprojection off-screen keeps the history", "taa_resolve_reproject",
+     "h = np.where(valid[:, None], h, c)", "h = h"),
     ("resolve neighbourhood without the edge clamp", "taa_resolve",
      "pad = np.pad(cur, ((1, 1), (1, 1), (0, 0)), mode=\"edge\")",
      "pad = np.pad(cur, ((1, 1), (1, 1), (0, 0)), mode=\"constant\")"),

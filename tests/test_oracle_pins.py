@@ -564,3 +564,75 @@ def test_frame_jitter_mean_over_frames_matches_closed_form():
     expect = 4.0 * P * (-math.expm1(-2 * sig * H)) * math.tanh(x / 2) / x
     se = rgba[:, 0].std() / math.sqrt(n)
     assert abs(rgba[:, 0].mean() - expect) < 4 * se
+
+
+# ---------------------------------------------------------------------------
+# Representative depth and the reprojected resolve (reading R18)
+# ---------------------------------------------------------------------------
+
+def test_depth_homogeneous_slab_matches_continuous_mean():
+    # opacity-weighted mean distance in a homogeneous slab of length L:
+    # int s sigma e^{-sigma s} ds / (1 - e^{-sigma L}) over [0, L]
+    for c, alpha in ((1.0, 3.0), (0.5, 1.0), (2.0, 10.0)):
+        sig, L = c * alpha, 1.0
+        p = params(steps=4096, alpha=alpha, jitter=0, light_steps=0)
+        o = np.array([[0.0, 2.0, 0.0]])
+        d = np.array([[0.0, -1.0, 0.0]])
+        _, depth = O.march_rays(const_volume(c), o, d, p, return_depth=True)
+        mean = (1.0 - (1.0 + sig * L) * math.exp(-sig * L)) / (sig * (1.0 - math.exp(-sig * L)))
+        assert abs(depth[0] - (1.5 + mean)) < 1e-6
+
+
+def test_depth_low_alpha_and_misses():
+    p = params(steps=16, alpha=1.0, jitter=0, light_steps=0)
+    o = np.array([[0.0, 2.0, 0.0], [0.3, 2.0, -0.2], [3.0, 2.0, 0.0]])
+    d = np.array([[0.0, -1.0, 0.0], [0.0, -1.0, 0.0], [0.0, -1.0, 0.0]])
+    rgba, depth = O.march_rays(const_volume(1e-4), o, d, p, return_depth=True)
+    assert rgba[0, 3] < O.DEPTH_ALPHA_MIN
+    assert abs(depth[0] - 2.0) < 1e-12 and abs(depth[1] - 2.0) < 1e-12   # chord middle
+    assert depth[2] == 0.0                                                   # miss
+
+
+def test_reproject_with_a_still_camera_is_the_plain_resolve():
+    rng = np.random.default_rng(4)
+    H, W = 23, 37
+    cur, hist = rng.random((H, W, 4)), rng.random((H, W, 4))
+    depth = np.where(rng.random((H, W)) < 0.3, 0.0, 1.0 + rng.random((H, W)))
+    cam = scenes.orbit_camera(2.0, 210.0, 20.0)
+    a = O.taa_resolve_reproject(cur, hist, depth, cam, cam, 0.1, 5)
+    b = O.taa_resolve(cur, hist, 0.1, 5)
+    assert np.max(np.abs(a - b)) < 1e-10
+    assert np.array_equal(O.taa_resolve_reproject(cur, hist, depth, cam, cam, 0.1, 0), cur)
+
+
+def test_reproject_sideways_translation_samples_the_parallax_shift():
+    # camera moved by delta along its right axis since the previous frame: a
+    # point at distance z along the view axis moves delta / z in the image
+    # plane; bilinear sampling of a linear history is exact inside the image
+    H, W, delta, beta = 30, 40, 0.1, 0.25
+    cam = scenes.orbit_camera(2.0, 210.0, 20.0)
+    pos = np.asarray(cam.pos, float)
+    f = np.asarray(cam.target, float) - pos
+    f /= np.linalg.norm(f)
+    r = np.cross(f, np.asarray(cam.up, float))
+    r /= np.linalg.norm(r)
+    prev = scenes.Camera(pos=tuple(pos - delta * r), target=tuple(np.asarray(cam.target) - delta * r),
+                         up=cam.up, vfov_deg=cam.vfov_deg)
+    py, px = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    depth = 1.0 + 0.02 * px + 0.03 * py
+    coef = np.array([[0.5, -0.2, 3.0], [0.1, 0.4, -1.0], [-0.3, 0.2, 0.5], [0.05, 0.05, 0.2]])
+    hist = np.stack([a * px + b * py + c for a, b, c in coef], axis=-1)
+    cur = np.where(((px + py) % 2 == 0)[..., None], 1e6, -1e6) * np.ones(4)
+    out = O.taa_resolve_reproject(cur, hist, depth, cam, prev, beta, 3)
+    _, d = O.camera_rays(cam, W, H, px.reshape(-1), py.reshape(-1))
+    z = depth.reshape(-1) * (d @ f)
+    tan_half = math.tan(math.radians(cam.vfov_deg) / 2)
+    u = px.reshape(-1) + delta / z * W / (2 * tan_half * W / H)
+    w = py.reshape(-1).astype(float)
+    inside = u <= W - 1
+    want = np.stack([a * u + b * w + c for a, b, c in coef], axis=-1)
+    got_h = (out.reshape(-1, 4) - beta * cur.reshape(-1, 4)) / (1 - beta)
+    assert np.max(np.abs(got_h[inside] - want[inside])) < 1e-6
+    outside = u > W - 0.5
+    assert outside.any()
+    assert np.array_equal(out.reshape(-1, 4)[outside], cur.reshape(-1, 4)[outside])

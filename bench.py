@@ -323,6 +323,28 @@ def quality_report(cf, scenes, torch) -> dict:
 
     one = cf.cloud_render(vol, cam, w2.params, 15, W, H).cpu().numpy()
     flat = cf.cloud_render(vol, cam, replace(w2.params, jitter=0), 15, W, H).cpu().numpy()
+    # the orbiting camera (1 degree per frame): plain against reprojected
+    # history, after 16 frames, against the 128-step render at the last camera
+    last = w2.camera(15)
+    ref_last = cf.cloud_render(vol, last, replace(w2.params, steps=128, jitter=0), 0, W,
+                               H).cpu().numpy()
+    plain_h = torch.zeros((H, W, 4), device="cuda")
+    bufs = [torch.zeros((H, W, 4), device="cuda") for _ in range(2)]
+    for f in range(16):
+        cf.cloud_render(vol, w2.camera(f), w2.params, f, W, H, out=cur)
+        cf.cloud_taa_resolve(cur, plain_h, plain_h, w2.taa_blend, f)
+        c2, dep = cf.cloud_render_depth(vol, w2.camera(f), w2.params, f, W, H)
+        cf.cloud_taa_resolve_reproject(c2, dep, bufs[(f + 1) % 2], bufs[f % 2], w2.camera(f),
+                                       w2.camera(max(f - 1, 0)), w2.taa_blend, f)
+
+    def err_last(a):
+        d = np.abs(a.astype(np.float64) - ref_last)
+        return {"mean_abs": float(d.mean()), "p99_abs": float(np.percentile(d, 99)),
+                "max_abs": float(d.max())}
+
+    out["orbit_16_frames_vs_128_C2"] = {"plain_taa": err_last(plain_h.cpu().numpy()),
+                                        "reprojected_taa": err_last(bufs[15 % 2].cpu().numpy()),
+                                        "one_frame": err_last(cur.cpu().numpy())}
     out["steps8_vs_128_C2"] = {"jitter_taa_16_frames": err(accumulated(1)),
                               "jitter_one_frame": err(one), "no_jitter": err(flat),
                               "tile_jitter_taa_16_frames": err(accumulated(2)),
@@ -347,6 +369,9 @@ def main():
     ap.add_argument("--served-dtype", default="f16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--served-layout", default="oct", choices=["dense", "quad", "oct"])
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--taa", default="plain", choices=["plain", "reproject"],
+                    help="temporal resolve: plain (the history as is) or reprojected through "
+                         "the previous camera with the render's depth")
     ap.add_argument("--jitter-mode", type=int, default=None, choices=[0, 1, 2, 3],
                     help="start offsets: 0 none, 1 per pixel (the workload's), 2 per 8x8 tile, "
                          "3 per frame")
@@ -435,12 +460,25 @@ def main():
     V = w.views
     cur = torch.empty((V, H, W, 4), device=dev)
     hist = torch.zeros((V, H, W, 4), device=dev)
+    reproject = args.taa == "reproject"
+    if reproject:
+        assert V == 1, "the reprojected resolve is measured on single-view workloads"
+        depth = torch.empty((H, W), device=dev)
+        hist2 = torch.zeros((H, W, 4), device=dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
 
     def frame(f, events=None):
         if events:
             events[0].record()
+        if reproject:
+            cf.cloud_render_depth(vol, w.camera(f), p, f, W, H, out=cur[0], depth=depth)
+            if events:
+                events[1].record()
+            src, dst = (hist[0], hist2) if f % 2 == 0 else (hist2, hist[0])
+            cf.cloud_taa_resolve_reproject(cur[0], depth, src, dst, w.camera(f),
+                                           w.camera(max(f - 1, 0)), w.taa_blend, f)
+            return
         if V == 1:
             cf.cloud_render(vol, w.camera(f), p, f, W, H, out=cur[0])
         else:
@@ -487,7 +525,7 @@ def main():
                 f"({args.dtype} storage, {args.layout} layout), orbiting camera",
         "config": {"workload": f"{w.name}: {w.description}", "width": W, "height": H,
                    "primary_steps": p.steps, "light_steps": p.light_steps, "jitter": JITTER_NAMES[p.jitter],
-                   "integration": "analytic", "taa_blend": w.taa_blend,
+                   "integration": "analytic", "taa_blend": w.taa_blend, "taa": args.taa,
                    "volume": f"{w.volume.n}^3 {args.dtype}", "layout": args.layout,
                    "occupancy_skip": not args.no_occupancy,
                    "lookups_per_frame": round(lk_frame)},

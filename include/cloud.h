@@ -202,6 +202,39 @@ int cloud_taa_resolve(const float* current, const float* history, float* out,
                       int32_t width, int32_t height, float blend,
                       uint32_t frame_index, void* hip_stream);
 
+/* cloud_render plus each pixel's representative depth (for the reprojected
+ * resolve): out_depth (device [height][width] float32, 4-byte aligned,
+ * caller-owned, not overlapping out_rgba) gets the mean distance along the
+ * ray of the samples, weighted by the opacity each step adds (T before the
+ * step minus T after it), where the pixel's alpha >= 0.01; the middle of the
+ * ray's chord through the box where alpha < 0.01; 0 (a point at infinity)
+ * where the ray misses the box. The image equals cloud_render's. */
+int cloud_render_depth(const cloud_volume* volume, const cloud_camera* camera,
+                       const cloud_params* params, uint32_t frame_index,
+                       int32_t width, int32_t height, float* out_rgba,
+                       float* out_depth, void* hip_stream);
+
+/* Temporal resolve with camera reprojection (Section 3.2 names Playdead's
+ * TAA, whose history is reprojected). For each pixel, the point at its depth
+ * (from cloud_render_depth with `camera`) along its ray -- the ray's
+ * direction alone where depth is 0 -- is projected into prev_camera, the
+ * camera `history` was resolved with; the history is sampled there
+ * bilinearly with edge clamping, clamped into the current frame's 3x3
+ * neighbourhood min/max and blended, out = h + blend * (current - h). Where
+ * the point is behind prev_camera or outside its image the history is taken
+ * to be the current value. frame_index == 0 or history == NULL copies
+ * current (depth and cameras are then not read).
+ *  current, history, out  device [height][width][4] float32, 16-byte aligned.
+ *  depth                  device [height][width] float32.
+ *  out must not overlap current, history or depth (no in-place update: a
+ *  pixel reads the history at other pixels). 0 < blend <= 1. */
+int cloud_taa_resolve_reproject(const float* current, const float* depth,
+                                const float* history, float* out,
+                                const cloud_camera* camera,
+                                const cloud_camera* prev_camera,
+                                int32_t width, int32_t height, float blend,
+                                uint32_t frame_index, void* hip_stream);
+
 /* Adds to *out_count (device, one uint64, 8-byte aligned) the number of
  * trilinear density lookups cloud_render performs for this frame: one per
  * primary sample taken plus light_steps per sample with non-zero density,

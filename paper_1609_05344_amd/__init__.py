@@ -18,6 +18,8 @@ from ._lib import (  # noqa: F401
     cloud_march_rays,
     cloud_render,
     cloud_render_views,
+    cloud_render_depth,
+    cloud_taa_resolve_reproject,
     cloud_taa_resolve,
     cloud_tune,
     cloud_volume_occupancy,

@@ -91,6 +91,12 @@ def load():
     lib.cloud_count_lookups.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera),
                                         POINTER(cloud_params), c_uint32, c_int32, c_int32,
                                         c_void_p, c_void_p]
+    lib.cloud_render_depth.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera),
+                                       POINTER(cloud_params), c_uint32, c_int32, c_int32,
+                                       c_void_p, c_void_p, c_void_p]
+    lib.cloud_taa_resolve_reproject.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p,
+                                                POINTER(cloud_camera), POINTER(cloud_camera),
+                                                c_int32, c_int32, c_float, c_uint32, c_void_p]
     lib.cloud_lookup_trace.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,
                                        POINTER(cloud_params), c_uint32, c_int32, c_int32,
                                        c_void_p, c_void_p]
@@ -102,7 +108,8 @@ def load():
                                       POINTER(cloud_volume), c_void_p]
     for name in ("cloud_render", "cloud_render_views", "cloud_march_rays", "cloud_taa_resolve",
                  "cloud_jitter_offsets", "cloud_check_buffer", "cloud_count_lookups",
-                 "cloud_lookup_trace", "cloud_gather_ceiling",
+                 "cloud_lookup_trace", "cloud_gather_ceiling", "cloud_render_depth",
+                 "cloud_taa_resolve_reproject",
                  "cloud_volume_packed_bytes", "cloud_volume_pack", "cloud_tune"):
         getattr(lib, name).restype = c_int
     _lib = lib
@@ -245,6 +252,36 @@ def cloud_count_lookups(volume: Volume, camera, params, frame_index: int, width:
     check(load().cloud_count_lookups(ctypes.byref(volume.struct), ctypes.byref(cam),
                                      ctypes.byref(prm), int(frame_index) & 0xFFFFFFFF, int(width),
                                      int(height), _ptr(out), _stream(stream)))
+    return out
+
+
+def cloud_render_depth(volume: Volume, camera, params, frame_index: int, width: int, height: int,
+                       out=None, depth=None, stream=None):
+    """cloud_render plus the representative depth; returns (rgba [H,W,4],
+    depth [H,W])."""
+    import torch
+    out = _out(out, (height, width, 4), volume.base.device)
+    if depth is None:
+        depth = torch.empty((height, width), dtype=torch.float32, device=volume.base.device)
+    cam, prm = make_camera(camera), make_params(params)
+    check(load().cloud_render_depth(ctypes.byref(volume.struct), ctypes.byref(cam),
+                                    ctypes.byref(prm), int(frame_index) & 0xFFFFFFFF, int(width),
+                                    int(height), _ptr(out), _ptr(depth), _stream(stream)))
+    return out, depth
+
+
+def cloud_taa_resolve_reproject(current, depth, history, out, camera, prev_camera, blend: float,
+                                frame_index: int, stream=None):
+    """Reprojected temporal resolve into `out` (which must not alias the
+    inputs); returns out."""
+    H, W = int(current.shape[0]), int(current.shape[1])
+    if out is None:
+        out = _out(None, (H, W, 4), current.device)
+    cam, prev = make_camera(camera), make_camera(prev_camera)
+    check(load().cloud_taa_resolve_reproject(_ptr(current), _ptr(depth), _ptr(history), _ptr(out),
+                                             ctypes.byref(cam), ctypes.byref(prev), W, H,
+                                             float(blend), int(frame_index) & 0xFFFFFFFF,
+                                             _stream(stream)))
     return out
 
 

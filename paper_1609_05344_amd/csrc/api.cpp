@@ -286,7 +286,7 @@ int cloud_abi_version(void) { return CLOUD_ABI_VERSION; }
 static int render_impl(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
                        const cloud_params* params, uint32_t frame_index, int32_t width,
                        int32_t height, float* out_rgba, uint64_t* counts, uint32_t* trace,
-                       void* hip_stream) {
+                       float* depth, void* hip_stream) {
   clear_error();
   if (!cameras) return fail(CLOUD_E_INVALID, "cameras is NULL");
   if (n_views < 1) return fail(CLOUD_E_INVALID, "n_views must be >= 1");
@@ -314,6 +314,14 @@ static int render_impl(const cloud_volume* volume, const cloud_camera* cameras, 
     if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
       return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
     if ((rc = check_span(out_rgba, px * 16 * (size_t)n_views, "out_rgba"))) return rc;
+    if (depth) {
+      if (reinterpret_cast<uintptr_t>(depth) % 4)
+        return fail(CLOUD_E_INVALID, "out_depth must be 4-byte aligned");
+      if ((rc = check_span(depth, px * 4 * (size_t)n_views, "out_depth"))) return rc;
+      const uintptr_t a = reinterpret_cast<uintptr_t>(out_rgba), b = reinterpret_cast<uintptr_t>(depth);
+      const size_t na = px * 16 * (size_t)n_views, nb = px * 4 * (size_t)n_views;
+      if (a < b + nb && b < a + na) return fail(CLOUD_E_INVALID, "out_depth overlaps out_rgba");
+    }
   }
   DevCameras cams;
   for (int i = 0; i < n_views; ++i) {
@@ -327,6 +335,7 @@ static int render_impl(const cloud_volume* volume, const cloud_camera* cameras, 
                                    height, image ? out_rgba + (size_t)first * px * 4 : nullptr,
                                    reinterpret_cast<unsigned long long*>(counts),
                                    trace ? trace + (size_t)first * px * 2 : nullptr,
+                                   image && depth ? depth + (size_t)first * px : nullptr,
                                    static_cast<hipStream_t>(hip_stream));
       if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("render launch: ") + hipGetErrorString(e));
     }
@@ -339,7 +348,7 @@ int cloud_render_views(const cloud_volume* volume, const cloud_camera* cameras, 
                        int32_t height, float* out_rgba, void* hip_stream) {
   CLOUD_GUARD_BEGIN
   return render_impl(volume, cameras, n_views, params, frame_index, width, height, out_rgba,
-                     nullptr, nullptr, hip_stream);
+                     nullptr, nullptr, nullptr, hip_stream);
   CLOUD_GUARD_END
 }
 
@@ -349,7 +358,7 @@ int cloud_count_lookups(const cloud_volume* volume, const cloud_camera* camera,
   CLOUD_GUARD_BEGIN
   if (!out_count) return fail(CLOUD_E_INVALID, "out_count is NULL");
   return render_impl(volume, camera, 1, params, frame_index, width, height, nullptr, out_count,
-                     nullptr, hip_stream);
+                     nullptr, nullptr, hip_stream);
   CLOUD_GUARD_END
 }
 
@@ -360,7 +369,7 @@ int cloud_lookup_trace(const cloud_volume* volume, const cloud_camera* cameras, 
   if (!out_trace) return fail(CLOUD_E_INVALID, "out_trace is NULL");
   if (!params) return fail(CLOUD_E_INVALID, "params is NULL");
   return render_impl(volume, cameras, n_views, params, frame_index, width, height, nullptr,
-                     nullptr, out_trace, hip_stream);
+                     nullptr, out_trace, nullptr, hip_stream);
   CLOUD_GUARD_END
 }
 
@@ -534,6 +543,57 @@ int cloud_taa_resolve(const float* current, const float* history, float* out, in
   }
   hipError_t e = launch_taa(current, history, out, width, height, blend, copy,
                             static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_render_depth(const cloud_volume* volume, const cloud_camera* camera,
+                       const cloud_params* params, uint32_t frame_index, int32_t width,
+                       int32_t height, float* out_rgba, float* out_depth, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  if (!out_depth) return fail(CLOUD_E_INVALID, "out_depth is NULL");
+  return render_impl(volume, camera, 1, params, frame_index, width, height, out_rgba, nullptr,
+                     nullptr, out_depth, hip_stream);
+  CLOUD_GUARD_END
+}
+
+int cloud_taa_resolve_reproject(const float* current, const float* depth, const float* history,
+                                float* out, const cloud_camera* camera,
+                                const cloud_camera* prev_camera, int32_t width, int32_t height,
+                                float blend, uint32_t frame_index, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  int rc = check_image(width, height, 1);
+  if (rc) return rc;
+  if (!std::isfinite(blend) || !(blend > 0.0f) || blend > 1.0f)
+    return fail(CLOUD_E_INVALID, "blend must be in (0, 1]");
+  const size_t bytes = (size_t)width * height * 16;
+  if ((rc = check_span(current, bytes, "current"))) return rc;
+  if ((rc = check_span(out, bytes, "out"))) return rc;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(current), b = reinterpret_cast<uintptr_t>(out);
+  if ((a | b | reinterpret_cast<uintptr_t>(history)) % 16)
+    return fail(CLOUD_E_INVALID, "images must be 16-byte aligned");
+  if (a < b + bytes && b < a + bytes) return fail(CLOUD_E_INVALID, "out overlaps current");
+  const bool copy = history == nullptr || frame_index == 0;
+  if (copy) {
+    hipError_t e = launch_taa(current, nullptr, out, width, height, blend, true,
+                              static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
+    return CLOUD_OK;
+  }
+  if ((rc = check_span(history, bytes, "history"))) return rc;
+  if ((rc = check_span(depth, bytes / 4, "depth"))) return rc;
+  if (reinterpret_cast<uintptr_t>(depth) % 4) return fail(CLOUD_E_INVALID, "depth must be 4-byte aligned");
+  const uintptr_t h = reinterpret_cast<uintptr_t>(history), dp = reinterpret_cast<uintptr_t>(depth);
+  if (h < b + bytes && b < h + bytes)
+    return fail(CLOUD_E_INVALID, "out overlaps history (a reprojected resolve cannot run in place)");
+  if (dp < b + bytes && b < dp + bytes / 4) return fail(CLOUD_E_INVALID, "out overlaps depth");
+  DevCamera cam, prev;
+  if ((rc = prepare_camera(camera, width, height, &cam))) return rc;
+  if ((rc = prepare_camera(prev_camera, width, height, &prev))) return rc;
+  hipError_t e = launch_taa_reproject(current, depth, history, out, cam, prev, width, height, blend,
+                                      static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
   return CLOUD_OK;
   CLOUD_GUARD_END

@@ -461,15 +461,22 @@ struct RayResult {
   // taken (up to the early exit), and bit i set when sample i (i < 32) ran a
   // light march
   uint32_t lookups, primary, light_mask;
+  // on request: the ray's representative depth -- the mean sample distance
+  // weighted by the opacity each step adds, where alpha >= kDepthAlphaMin;
+  // the middle of the ray's chord through the box below that; 0 (at
+  // infinity) when the ray misses the box
+  float depth;
 };
+
+constexpr float kDepthAlphaMin = 0.01f;
 
 // One primary ray through the volume (Sections 1, 3.1, 3.2). (o, d): origin
 // and unit direction; j: start offset in [0, 1).
-template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+template <int DT, int LAYOUT, bool DETAIL, bool COUNT, bool DEPTH = false>
 __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& P, float ox,
                                            float oy, float oz, float dx, float dy, float dz,
                                            float j) {
-  RayResult res = {0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+  RayResult res = {0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, 0u, 0.0f};
   float tn, tf;
   if (!ray_box(v, ox, oy, oz, dx, dy, dz, tn, tf)) return res;
 
@@ -482,6 +489,7 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
   const float xD = P.alpha * D;         // optical depth per unit density for one step
 
   float T = 1.0f, Sr = 0.0f, Sg = 0.0f, Sb = 0.0f;
+  float td = 0.0f;   // sum of (opacity added) x (sample distance), for DEPTH
   uint32_t n = 0, prim = 0, mask = 0;
 #if CLOUD_PREFETCH
   // The next sample's density is fetched before this sample's light march,
@@ -521,6 +529,7 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
       const float lr = fmaf(sr, TL, P.amb[0]), lg = fmaf(sg, TL, P.amb[1]),
                   lb = fmaf(sb, TL, P.amb[2]);
       const float e = exp2f(-rho * kx);
+      const float T_before = T;
       float w;
       if (P.integration) {
         // Section 3.1: T0 L_in (1 - e^{-rho alpha D}), then the T update
@@ -534,6 +543,7 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
       Sr = fmaf(w, lr, Sr);
       Sg = fmaf(w, lg, Sg);
       Sb = fmaf(w, lb, Sb);
+      if constexpr (DEPTH) td = fmaf(T_before - T, t, td);
       if (T < P.t_eps) break;
     }
   }
@@ -541,6 +551,7 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
   res.g = Sg;
   res.b = Sb;
   res.a = 1.0f - T;
+  if constexpr (DEPTH) res.depth = res.a >= kDepthAlphaMin ? td / res.a : 0.5f * (tn + tf);
   res.lookups = n;
   res.primary = prim;
   res.light_mask = mask;

@@ -30,11 +30,17 @@ int render_residency(int dtype, int layout, bool detail);
 // Render n_views (<= kMaxViews) cameras into out [n_views][H][W][4]. With
 // counts or trace given, store no image: add the density lookups to *counts
 // and/or write each pixel's (primary samples, light-march mask) to trace
-// [n_views][H][W][2].
+// [n_views][H][W][2]. With depth given, also store each pixel's
+// representative depth in depth [n_views][H][W].
 hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevParams& p,
                          const DevCameras& c, int n_views, uint32_t frame, int W, int H,
                          float* out, unsigned long long* counts, uint32_t* trace,
-                         hipStream_t s);
+                         float* depth, hipStream_t s);
+
+// Temporal resolve with camera reprojection (out must not alias hist).
+hipError_t launch_taa_reproject(const float* cur, const float* depth, const float* hist,
+                                float* out, const DevCamera& cam, const DevCamera& prev, int W,
+                                int H, float blend, hipStream_t s);
 
 // Fetch-only replay of a render's lookups (random == false: the positions
 // recorded in trace; random == true: as many lookups per pixel at uniformly

@@ -18,9 +18,10 @@ Tuning& tuning() {
 // cloud_render / cloud_render_views / cloud_count_lookups: one thread per
 // pixel. A 256-thread workgroup covers a 16x16 pixel tile as four 8x8 wave
 // tiles, so the 64 rays of a wavefront are a compact bundle that samples
-// neighbouring texels. COUNT adds up the density lookups (into counts, if
-// given) and records each pixel's (primary samples, light-march mask) pair
-// (into trace, if given) instead of storing the image.
+// neighbouring texels. MODE kImage stores the image; kCount adds up the
+// density lookups (into counts, if given) and records each pixel's (primary
+// samples, light-march mask) pair (into trace, if given) instead; kDepth
+// stores the image and each pixel's representative depth (into depth).
 // ---------------------------------------------------------------------------
 
 // Minimum waves per SIMD the register allocator must leave room for (0: the
@@ -34,13 +35,17 @@ Tuning& tuning() {
 #define CLOUD_RENDER_ATTR
 #endif
 
-template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+enum { kImage = 0, kCount = 1, kDepth = 2 };
+
+template <int DT, int LAYOUT, bool DETAIL, int MODE>
 __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume vol, DevParams prm,
                                                      DevCameras cams, uint32_t frame, int W,
                                                      int H, int tiles_x, int tiles_y, int S,
                                                      float4* __restrict__ out,
                                                      unsigned long long* __restrict__ counts,
-                                                     uint2* __restrict__ trace) {
+                                                     uint2* __restrict__ trace,
+                                                     float* __restrict__ depth) {
+  constexpr bool COUNT = MODE == kCount;
   const int tiles_per_view = tiles_x * tiles_y;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int view = tile / tiles_per_view;
@@ -53,13 +58,14 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
   stage_occupancy(vol);
   if (!COUNT && !inside) return;
 
-  RayResult r = {0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+  RayResult r = {0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, 0u, 0.0f};
   if (inside) {
     const DevCamera& c = cams.c[view];
     float dx, dy, dz;
     camera_dir(c, px, py, W, H, dx, dy, dz);
     const float j = jitter_for(prm.jitter, (uint32_t)px, (uint32_t)py, frame, prm.seed);
-    r = march<DT, LAYOUT, DETAIL, COUNT>(vol, prm, c.pos[0], c.pos[1], c.pos[2], dx, dy, dz, j);
+    r = march<DT, LAYOUT, DETAIL, COUNT, MODE == kDepth>(vol, prm, c.pos[0], c.pos[1], c.pos[2],
+                                                         dx, dy, dz, j);
   }
   if constexpr (COUNT) {
     if (counts) {
@@ -68,7 +74,9 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
     }
     if (trace && inside) trace[((size_t)view * H + py) * W + px] = make_uint2(r.primary, r.light_mask);
   } else {
-    out[((size_t)view * H + py) * W + px] = make_float4(r.r, r.g, r.b, r.a);
+    const size_t pix = ((size_t)view * H + py) * W + px;
+    out[pix] = make_float4(r.r, r.g, r.b, r.a);
+    if constexpr (MODE == kDepth) depth[pix] = r.depth;
   }
 }
 
@@ -191,28 +199,35 @@ __global__ __launch_bounds__(256) void jitter_kernel(const uint32_t* __restrict_
 // Launchers: runtime (dtype, layout, detail, count) -> template instance
 // ---------------------------------------------------------------------------
 
+template <typename F, int DT, int LAYOUT, bool DETAIL>
+static hipError_t dispatch_m(int mode, F& f) {
+  switch (mode) {
+    case kCount: return f.template run<DT, LAYOUT, DETAIL, kCount>();
+    case kDepth: return f.template run<DT, LAYOUT, DETAIL, kDepth>();
+    default: return f.template run<DT, LAYOUT, DETAIL, kImage>();
+  }
+}
+
 template <typename F, int DT, int LAYOUT>
-static hipError_t dispatch_dc(bool detail, bool count, F& f) {
-  if (detail) return count ? f.template run<DT, LAYOUT, true, true>()
-                           : f.template run<DT, LAYOUT, true, false>();
-  return count ? f.template run<DT, LAYOUT, false, true>() : f.template run<DT, LAYOUT, false, false>();
+static hipError_t dispatch_dc(bool detail, int mode, F& f) {
+  return detail ? dispatch_m<F, DT, LAYOUT, true>(mode, f) : dispatch_m<F, DT, LAYOUT, false>(mode, f);
 }
 
 template <typename F, int DT>
-static hipError_t dispatch_l(int layout, bool detail, bool count, F& f) {
+static hipError_t dispatch_l(int layout, bool detail, int mode, F& f) {
   switch (layout) {
-    case LAYOUT_QUAD: return dispatch_dc<F, DT, LAYOUT_QUAD>(detail, count, f);
-    case LAYOUT_OCT: return dispatch_dc<F, DT, LAYOUT_OCT>(detail, count, f);
-    default: return dispatch_dc<F, DT, LAYOUT_DENSE>(detail, count, f);
+    case LAYOUT_QUAD: return dispatch_dc<F, DT, LAYOUT_QUAD>(detail, mode, f);
+    case LAYOUT_OCT: return dispatch_dc<F, DT, LAYOUT_OCT>(detail, mode, f);
+    default: return dispatch_dc<F, DT, LAYOUT_DENSE>(detail, mode, f);
   }
 }
 
 template <typename F>
-static hipError_t dispatch(int dtype, int layout, bool detail, bool count, F& f) {
+static hipError_t dispatch(int dtype, int layout, bool detail, int mode, F& f) {
   switch (dtype) {
-    case DT_F16: return dispatch_l<F, DT_F16>(layout, detail, count, f);
-    case DT_BF16: return dispatch_l<F, DT_BF16>(layout, detail, count, f);
-    default: return dispatch_l<F, DT_F32>(layout, detail, count, f);
+    case DT_F16: return dispatch_l<F, DT_F16>(layout, detail, mode, f);
+    case DT_BF16: return dispatch_l<F, DT_BF16>(layout, detail, mode, f);
+    default: return dispatch_l<F, DT_F32>(layout, detail, mode, f);
   }
 }
 
@@ -267,8 +282,8 @@ static int render_cap() {
 
 template <int DT, int LAYOUT, bool DETAIL>
 static int residency_of() {
-  const void* fn = reinterpret_cast<const void*>(render_kernel<DT, LAYOUT, DETAIL, false>);
-  static const size_t slds = static_lds_of(render_kernel<DT, LAYOUT, DETAIL, false>);
+  const void* fn = reinterpret_cast<const void*>(render_kernel<DT, LAYOUT, DETAIL, kImage>);
+  static const size_t slds = static_lds_of(render_kernel<DT, LAYOUT, DETAIL, kImage>);
   const long long pad = residency_lds(render_cap<DT, LAYOUT>(), slds);
   int n = 0;
   if (pad < 0 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, (size_t)pad) != hipSuccess)
@@ -277,7 +292,7 @@ static int residency_of() {
 }
 
 struct ResidencyQuery {
-  template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+  template <int DT, int LAYOUT, bool DETAIL, int MODE>
   hipError_t run() {
     n = residency_of<DT, LAYOUT, DETAIL>();
     return hipSuccess;
@@ -295,22 +310,24 @@ struct RenderLaunch {
   float* out;
   unsigned long long* counts;
   uint32_t* trace;
+  float* depth;
   hipStream_t s;
-  template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+  template <int DT, int LAYOUT, bool DETAIL, int MODE>
   hipError_t run() {
     const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
     const int tiles_per_view = tiles_x * tiles_y;
     const int blocks = tiles_per_view * n_views;
     size_t lds = 0;
-    if (!COUNT && render_cap<DT, LAYOUT>() > 0) {
-      static const size_t slds = static_lds_of(render_kernel<DT, LAYOUT, DETAIL, COUNT>);
+    if (MODE != kCount && render_cap<DT, LAYOUT>() > 0) {
+      static const size_t slds = static_lds_of(render_kernel<DT, LAYOUT, DETAIL, MODE>);
       const long long pad = residency_lds(render_cap<DT, LAYOUT>(), slds);
       if (pad < 0) return hipErrorInvalidValue;
       lds = (size_t)pad;
     }
-    hipLaunchKernelGGL((render_kernel<DT, LAYOUT, DETAIL, COUNT>), dim3(blocks), dim3(256), lds, s,
+    hipLaunchKernelGGL((render_kernel<DT, LAYOUT, DETAIL, MODE>), dim3(blocks), dim3(256), lds, s,
                        v, p, c, frame, W, H, tiles_x, tiles_y, tuning().supertile,
-                       reinterpret_cast<float4*>(out), counts, reinterpret_cast<uint2*>(trace));
+                       reinterpret_cast<float4*>(out), counts, reinterpret_cast<uint2*>(trace),
+                       depth);
     return hipGetLastError();
   }
 };
@@ -324,7 +341,7 @@ struct RaysLaunch {
   long long n;
   float* out;
   hipStream_t s;
-  template <int DT, int LAYOUT, bool DETAIL, bool COUNT>
+  template <int DT, int LAYOUT, bool DETAIL, int MODE>
   hipError_t run() {
     const long long blocks = (n + 255) / 256;
     hipLaunchKernelGGL((rays_kernel<DT, LAYOUT, DETAIL>), dim3((unsigned)blocks), dim3(256), 0, s,
@@ -336,14 +353,15 @@ struct RaysLaunch {
 hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevParams& p,
                          const DevCameras& c, int n_views, uint32_t frame, int W, int H,
                          float* out, unsigned long long* counts, uint32_t* trace,
-                         hipStream_t s) {
-  RenderLaunch f{v, p, c, n_views, frame, W, H, out, counts, trace, s};
-  return dispatch(dtype, layout, v.detail != nullptr, counts != nullptr || trace != nullptr, f);
+                         float* depth, hipStream_t s) {
+  RenderLaunch f{v, p, c, n_views, frame, W, H, out, counts, trace, depth, s};
+  const int mode = counts != nullptr || trace != nullptr ? kCount : depth != nullptr ? kDepth : kImage;
+  return dispatch(dtype, layout, v.detail != nullptr, mode, f);
 }
 
 int render_residency(int dtype, int layout, bool detail) {
   ResidencyQuery q;
-  dispatch(dtype, layout, detail, false, q);
+  if (dispatch(dtype, layout, detail, kImage, q) != hipSuccess) return 0;
   return q.n;
 }
 
@@ -351,7 +369,7 @@ hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParam
                        uint32_t frame, const float* o, const float* d, const uint32_t* pxy,
                        long long n, float* out, hipStream_t s) {
   RaysLaunch f{v, p, frame, o, d, pxy, n, out, s};
-  return dispatch(dtype, layout, v.detail != nullptr, false, f);
+  return dispatch(dtype, layout, v.detail != nullptr, kImage, f);
 }
 
 hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,

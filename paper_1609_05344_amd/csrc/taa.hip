@@ -1,6 +1,7 @@
 // Temporal resolve kernels and their launcher.
 #include <hip/hip_runtime.h>
 
+#include "cloud_device.h"
 #include "cloud_launch.h"
 
 namespace cloud {
@@ -54,6 +55,100 @@ __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ sr
                                                    float4* __restrict__ dst, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Temporal resolve with camera reprojection (Section 3.2 names Playdead's
+// TAA, which reprojects its history): the point at the pixel's
+// representative depth along its ray (at infinity for depth 0) is projected
+// into the previous camera and the history is sampled there bilinearly
+// (edge-clamped), then clamped into the current 3x3 neighbourhood (staged in
+// LDS as above) and blended. A point behind the previous camera or outside
+// its image takes the current value as its history.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
+  return make_float4(fmaf(w, b.x - a.x, a.x), fmaf(w, b.y - a.y, a.y), fmaf(w, b.z - a.z, a.z),
+                     fmaf(w, b.w - a.w, a.w));
+}
+
+template <int TW>
+__global__ __launch_bounds__(256) void taa_reproject_kernel(const float4* __restrict__ cur,
+                                                            const float* __restrict__ depth,
+                                                            const float4* __restrict__ hist,
+                                                            float4* __restrict__ out, DevCamera cam,
+                                                            DevCamera prev, int W, int H,
+                                                            int tiles_x, float blend) {
+  constexpr int TH = 256 / TW;
+  __shared__ float4 tile[TH + 2][TW + 2];
+  const int tyi = blockIdx.x / tiles_x, txi = blockIdx.x - tyi * tiles_x;
+  const int bx = txi * TW, by = tyi * TH;
+  for (int i = threadIdx.x; i < (TH + 2) * (TW + 2); i += 256) {
+    const int ly = i / (TW + 2), lx = i - ly * (TW + 2);
+    const int gx = min(max(bx + lx - 1, 0), W - 1);
+    const int gy = min(max(by + ly - 1, 0), H - 1);
+    tile[ly][lx] = cur[(size_t)gy * W + gx];
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int px = bx + lx, py = by + ly;
+  if (px >= W || py >= H) return;
+  const float4 c = tile[ly + 1][lx + 1];
+  float4 lo = c, hi = c;
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const float4 v = tile[ly + dy][lx + dx];
+      lo.x = fminf(lo.x, v.x); lo.y = fminf(lo.y, v.y); lo.z = fminf(lo.z, v.z); lo.w = fminf(lo.w, v.w);
+      hi.x = fmaxf(hi.x, v.x); hi.y = fmaxf(hi.y, v.y); hi.z = fmaxf(hi.z, v.z); hi.w = fmaxf(hi.w, v.w);
+    }
+  }
+  const size_t p = (size_t)py * W + px;
+  float dx, dy, dz;
+  camera_dir(cam, px, py, W, H, dx, dy, dz);
+  const float dep = depth[p];
+  float vx = dx, vy = dy, vz = dz;
+  if (dep > 0.0f) {
+    vx = fmaf(dep, dx, cam.pos[0]) - prev.pos[0];
+    vy = fmaf(dep, dy, cam.pos[1]) - prev.pos[1];
+    vz = fmaf(dep, dz, cam.pos[2]) - prev.pos[2];
+  }
+  const float z = vx * prev.fwd[0] + vy * prev.fwd[1] + vz * prev.fwd[2];
+  const float x = (vx * prev.right[0] + vy * prev.right[1] + vz * prev.right[2]) / z;
+  const float y = (vx * prev.up[0] + vy * prev.up[1] + vz * prev.up[2]) / z;
+  const float uc = (x / (prev.tan_half * prev.aspect) + 1.0f) * (0.5f * (float)W) - 0.5f;
+  const float wc = (1.0f - y / prev.tan_half) * (0.5f * (float)H) - 0.5f;
+  float4 h = c;
+  // NaN and infinite coordinates fail these comparisons too
+  if (z > 0.0f && uc >= -0.5f && uc <= (float)W - 0.5f && wc >= -0.5f && wc <= (float)H - 0.5f) {
+    const float x0f = floorf(uc), y0f = floorf(wc);
+    const float fx = uc - x0f, fy = wc - y0f;
+    const int x0 = (int)x0f, y0 = (int)y0f;   // in [-1, W-1] and [-1, H-1]
+    const int xa = max(x0, 0), xb = min(x0 + 1, W - 1);
+    const int ya = max(y0, 0), yb = min(y0 + 1, H - 1);
+    const float4 top = lerp4(hist[(size_t)ya * W + xa], hist[(size_t)ya * W + xb], fx);
+    const float4 bot = lerp4(hist[(size_t)yb * W + xa], hist[(size_t)yb * W + xb], fx);
+    h = lerp4(top, bot, fy);
+  }
+  h.x = fminf(fmaxf(h.x, lo.x), hi.x);
+  h.y = fminf(fmaxf(h.y, lo.y), hi.y);
+  h.z = fminf(fmaxf(h.z, lo.z), hi.z);
+  h.w = fminf(fmaxf(h.w, lo.w), hi.w);
+  out[p] = make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
+                       fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w));
+}
+
+hipError_t launch_taa_reproject(const float* cur, const float* depth, const float* hist,
+                                float* out, const DevCamera& cam, const DevCamera& prev, int W,
+                                int H, float blend, hipStream_t s) {
+  constexpr int TW = 32, TH = 256 / TW;
+  const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+  hipLaunchKernelGGL(taa_reproject_kernel<TW>, dim3(tiles_x * tiles_y), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(cur), depth,
+                     reinterpret_cast<const float4*>(hist), reinterpret_cast<float4*>(out), cam,
+                     prev, W, H, tiles_x, blend);
+  return hipGetLastError();
 }
 
 hipError_t launch_taa(const float* cur, const float* hist, float* out, int W, int H, float blend,

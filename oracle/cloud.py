@@ -560,3 +560,37 @@ def taa_resolve_reproject(cur, hist, depth, cam, prev_cam, blend: float, frame_i
     lo, hi = nb.min(axis=0).reshape(-1, 4), nb.max(axis=0).reshape(-1, 4)
     h = np.minimum(np.maximum(h, lo), hi)
     return (h + blend * (c - h)).reshape(H, W, 4)
+
+
+# ---------------------------------------------------------------------------
+# Composite of the resolved low-resolution cloud layer into the scene
+# (Section 3.2; reading R19)
+# ---------------------------------------------------------------------------
+
+def upsample_bilinear(img, width: int, height: int):
+    """Bilinear resize of img [h][w][c] to [height][width][c] with pixel
+    centres aligned: output pixel x samples the input at (x + 1/2) w / width
+    - 1/2 (likewise in y), edge-clamped."""
+    img = np.asarray(img, dtype=np.float64)
+    h, w = img.shape[:2]
+    uc = (np.arange(width) + 0.5) * (w / width) - 0.5
+    vc = (np.arange(height) + 0.5) * (h / height) - 0.5
+    x0f, y0f = np.floor(uc), np.floor(vc)
+    fx, fy = (uc - x0f)[None, :, None], (vc - y0f)[:, None, None]
+    x0 = np.clip(x0f.astype(np.int64), 0, w - 1)
+    x1 = np.clip(x0f.astype(np.int64) + 1, 0, w - 1)
+    y0 = np.clip(y0f.astype(np.int64), 0, h - 1)
+    y1 = np.clip(y0f.astype(np.int64) + 1, 0, h - 1)
+    top = _lerp(img[y0][:, x0], img[y0][:, x1], fx)
+    bot = _lerp(img[y1][:, x0], img[y1][:, x1], fx)
+    return _lerp(top, bot, fy)
+
+
+def composite(cloud, background):
+    """Premultiplied cloud layer (any resolution) over the background
+    [height][width][4]: the layer is up-sampled bilinearly to the background's
+    size, then out = c + (1 - c_alpha) * bg in every channel."""
+    bg = np.asarray(background, dtype=np.float64)
+    H, W = bg.shape[:2]
+    c = upsample_bilinear(cloud, W, H)
+    return c + (1.0 - c[..., 3:4]) * bg

@@ -273,6 +273,7 @@ class Workload:
     detail_seed: int = 33
     views: int = 1
     description: str = ""
+    display: tuple = ()         # (width, height) the cloud layer is composited at; () = none
 
     def camera(self, frame: int = 0, view: int = 0) -> Camera:
         """Orbit advancing 1 degree per frame; views spread 45 degrees apart."""
@@ -306,6 +307,18 @@ WORKLOADS = {
         Params(steps=8, alpha=10.0, g=0.6, jitter=1),
         radius=1.0, elevation_deg=10.0, frames=16,
         description="1080p, 256^3 f32 slab layer, 8 jittered steps, 6 light steps, TAA"),
+    "Hh": Workload(
+        "Hh", 960, 540, VolumeSpec(256, 5, 0.45, seed=2, height_falloff=True), "f32",
+        Params(steps=8, alpha=10.0, g=0.6, jitter=1),
+        radius=1.0, elevation_deg=10.0, frames=16, display=(1920, 1080),
+        description="half-resolution cloud layer (960x540) of H, resolved, up-sampled and "
+                    "composited over a 1920x1080 sky"),
+    "Hq": Workload(
+        "Hq", 480, 270, VolumeSpec(256, 5, 0.45, seed=2, height_falloff=True), "f32",
+        Params(steps=8, alpha=10.0, g=0.6, jitter=1),
+        radius=1.0, elevation_deg=10.0, frames=16, display=(1920, 1080),
+        description="quarter-resolution cloud layer (480x270) of H, resolved, up-sampled and "
+                    "composited over a 1920x1080 sky"),
     "C5": Workload(
         "C5", 3840, 2160, VolumeSpec(512, 6, 0.5, seed=5), "f16",
         Params(steps=8, alpha=10.0, g=0.6, jitter=1),
@@ -323,6 +336,22 @@ def workload(name: str, **overrides) -> Workload:
             wov["params"] = replace(w.params, **pov)
         w = replace(w, **wov)
     return w
+
+
+def sky_background(width: int, height: int) -> np.ndarray:
+    """A [height][width][4] float32 sky (opaque, alpha 1) to composite the cloud
+    layer over: a vertical blend from a pale horizon (bottom row) to a deeper
+    zenith colour (top row), with a faint horizontal tint so that rows are
+    not constant. Input data only."""
+    v = 1.0 - (np.arange(height, dtype=np.float64) + 0.5) / height      # 1 at the top
+    u = (np.arange(width, dtype=np.float64) + 0.5) / width
+    horizon = np.array([0.80, 0.85, 0.95])
+    zenith = np.array([0.20, 0.40, 0.85])
+    w = np.sqrt(v)[:, None, None]
+    rgb = horizon[None, None, :] * (1.0 - w) + zenith[None, None, :] * w
+    rgb = rgb * (0.95 + 0.05 * u)[None, :, None]
+    out = np.concatenate([rgb, np.ones((height, width, 1))], axis=-1)
+    return out.astype(np.float32)
 
 
 @dataclass

@@ -54,6 +54,8 @@ PINS = {
                              P.test_frame_jitter_mean_over_frames_matches_closed_form()),
     "depth": lambda: (P.test_depth_homogeneous_slab_matches_continuous_mean(),
                       P.test_depth_low_alpha_and_misses()),
+    "composite": lambda: (P.test_composite_same_size_is_the_over_operator(),
+                          [P.test_upsample_linear_field_and_edges(f) for f in (2, 4)]),
     "reproject": lambda: (P.test_reproject_with_a_still_camera_is_the_plain_resolve(),
                           P.test_reproject_sideways_translation_samples_the_parallax_shift()),
 }
@@ -137,6 +139,10 @@ MUTATIONS = [
      "top = _lerp(hist[y0, x0], hist[y0, x1], fx)", "top = _lerp(hist[y0, x0], hist[y0, x1], fy)"),
     ("reprojection off-screen keeps the history", "taa_resolve_reproject",
      "h = np.where(valid[:, None], h, c)", "h = h"),
+    ("up-sample with corners aligned", "upsample_bilinear",
+     "uc = (np.arange(width) + 0.5) * (w / width) - 0.5", "uc = np.arange(width) * ((w - 1) / max(width - 1, 1))"),
+    ("composite weighted by the background alpha", "composite",
+     "return c + (1.0 - c[..., 3:4]) * bg", "return c + (1.0 - bg[..., 3:4]) * bg"),
     ("resolve neighbourhood without the edge clamp", "taa_resolve",
      "pad = np.pad(cur, ((1, 1), (1, 1), (0, 0)), mode=\"edge\")",
      "pad = np.pad(cur, ((1, 1), (1, 1), (0, 0)), mode=\"constant\")"),

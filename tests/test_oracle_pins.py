@@ -636,3 +636,43 @@ def test_reproject_sideways_translation_samples_the_parallax_shift():
     outside = u > W - 0.5
     assert outside.any()
     assert np.array_equal(out.reshape(-1, 4)[outside], cur.reshape(-1, 4)[outside])
+
+
+# ---------------------------------------------------------------------------
+# Composite of the cloud layer into the scene (reading R19)
+# ---------------------------------------------------------------------------
+
+def test_composite_same_size_is_the_over_operator():
+    rng = np.random.default_rng(8)
+    bg = rng.random((9, 13, 4))
+    a = rng.random((9, 13, 1))
+    cloud = np.concatenate([rng.random((9, 13, 3)) * a, a], axis=-1)
+    out = O.composite(cloud, bg)
+    # by hand, channel by channel, the over operator for premultiplied colour
+    for y, x in ((0, 0), (4, 7), (8, 12)):
+        for ch in range(4):
+            assert abs(out[y, x, ch] - (cloud[y, x, ch] + (1 - cloud[y, x, 3]) * bg[y, x, ch])) < 1e-15
+    clear = np.zeros((9, 13, 4))
+    assert np.array_equal(O.composite(clear, bg), bg)
+    opaque = cloud.copy()
+    opaque[..., 3] = 1.0
+    assert np.array_equal(O.composite(opaque, bg), opaque)
+
+
+@pytest.mark.parametrize("factor", [2, 4])
+def test_upsample_linear_field_and_edges(factor):
+    h, w = 6, 10
+    ly, lx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    img = np.stack([0.3 * lx + 0.1 * ly, -0.2 * lx + 0.5 * ly, lx * 0 + 1.0, 0.05 * lx], axis=-1)
+    up = O.upsample_bilinear(img, w * factor, h * factor)
+    Y, X = np.meshgrid(np.arange(h * factor), np.arange(w * factor), indexing="ij")
+    u = (X + 0.5) / factor - 0.5
+    v = (Y + 0.5) / factor - 0.5
+    want = np.stack([0.3 * u + 0.1 * v, -0.2 * u + 0.5 * v, u * 0 + 1.0, 0.05 * u], axis=-1)
+    inside = (u >= 0) & (u <= w - 1) & (v >= 0) & (v <= h - 1)
+    assert np.max(np.abs(up - want)[inside]) < 1e-12
+    # outside the centres of the edge pixels the edge value is held
+    left = u < 0
+    assert np.allclose(up[left][:, 0], 0.1 * np.clip(v[left], 0, h - 1) + 0.0)
+    # a factor-1 resize is the identity
+    assert np.array_equal(O.upsample_bilinear(img, w, h), img)

@@ -104,6 +104,71 @@ def cpu_baseline(name: str, dtype: str, frames: int, cores: int) -> dict:
 
 
 # ---------------------------------------------------------------------------
+# The paper's timing table (Section 4) on this GPU
+# ---------------------------------------------------------------------------
+
+PAPER_ROWS = [
+    # (label, workload giving the resolution, steps, jitter, resolve, paper's GTX 1080 ms)
+    ("Full, 128 steps", "H", 128, 0, False, 297.7),
+    ("Half, 128 steps", "Hh", 128, 0, False, 128.0),
+    ("Half, 8 steps", "Hh", 8, 0, False, 2.3),
+    ("Half, 8 steps, jitter", "Hh", 8, 1, False, 7.5),
+    ("Half, 8 steps, jitter, TAA", "Hh", 8, 1, True, 7.5),
+    ("Quarter, 8 steps, jitter, TAA", "Hq", 8, 1, True, 2.4),
+]
+
+
+def paper_table(cf, scenes, torch, np, dtype: str, layout: str, frames=range(10, 40)) -> dict:
+    """Each row of the paper's timing table: the cloud render at that
+    resolution and step count (H's volume and camera orbit), plus the
+    resolve and the up-sample + composite into the 1920x1080 frame where the
+    row has them. HIP-event means over the frames given; lookups counted by
+    the library outside the timed launches."""
+    from dataclasses import replace
+    base = scenes.workload("H")
+    vol = cf.device_volume(scenes.make_scene(base, dtype=dtype), layout=layout, occupancy=True)
+    sky = torch.tensor(scenes.sky_background(1920, 1080), device="cuda")
+    full = torch.empty((1080, 1920, 4), device="cuda")
+    rows = []
+    for label, wname, steps, jit, taa, paper_ms in PAPER_ROWS:
+        w = scenes.workload(wname)
+        W, H = w.width, w.height
+        p = replace(base.params, steps=steps, jitter=jit)
+        cur = torch.empty((H, W, 4), device="cuda")
+        hist = torch.zeros((H, W, 4), device="cuda")
+        lk = torch.zeros((1,), dtype=torch.int64, device="cuda")
+        for f in frames:
+            cf.cloud_count_lookups(vol, base.camera(f), p, f, W, H, out=lk)
+        n_lk = int(lk.item()) / len(frames)
+        ev = []
+        for f in frames:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record()
+            cf.cloud_render(vol, base.camera(f), p, f, W, H, out=cur)
+            e[1].record()
+            if taa:
+                cf.cloud_taa_resolve(cur, hist, hist, w.taa_blend, f - frames[0])
+            e[2].record()
+            if (W, H) != (1920, 1080):
+                cf.cloud_composite(hist if taa else cur, sky, out=full)
+            e[3].record()
+            ev.append(e)
+        torch.cuda.synchronize()
+        r = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        t = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        c = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
+        rows.append({"row": label, "width": W, "height": H, "render_ms": round(r, 4),
+                     "resolve_ms": round(t, 4) if taa else None,
+                     "composite_ms": round(c, 4) if (W, H) != (1920, 1080) else None,
+                     "total_ms": round(r + (t if taa else 0) + (c if (W, H) != (1920, 1080) else 0), 4),
+                     "lookups_per_frame": round(n_lk),
+                     "gsamples_per_s": round(n_lk / (r * 1e-3) / 1e9, 1),
+                     "paper_gtx1080_ms": paper_ms})
+    return {"metric": "the paper's timing table (Section 4) on MI355X", "unit": "ms",
+            "storage": f"{dtype} {layout}, occupancy skip", "frames": len(frames), "rows": rows}
+
+
+# ---------------------------------------------------------------------------
 # Gather ceiling: the render's own fetches with the arithmetic removed
 # ---------------------------------------------------------------------------
 
@@ -369,6 +434,8 @@ def main():
     ap.add_argument("--served-dtype", default="f16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--served-layout", default="oct", choices=["dense", "quad", "oct"])
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="time the rows of the paper's timing table and exit")
     ap.add_argument("--taa", default="plain", choices=["plain", "reproject"],
                     help="temporal resolve: plain (the history as is) or reprojected through "
                          "the previous camera with the render's depth")
@@ -393,10 +460,19 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(frames and streams are independent; see the sharding notes in DESIGN.md)",
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path (frames, views "
+              "and serving streams are independent, so each GPU would take whole ones)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.paper_table:
+        import numpy as np
+        import torch
+        import paper_1609_05344_amd as cf
+        from paper_1609_05344_amd import scenes
+        for dt, lay in (("f32", "quad"), ("f16", "oct")):
+            print(json.dumps(paper_table(cf, scenes, torch, np, dt, lay)), flush=True)
+        return
 
     if args.quality:
         import torch
@@ -465,10 +541,21 @@ def main():
         assert V == 1, "the reprojected resolve is measured on single-view workloads"
         depth = torch.empty((H, W), device=dev)
         hist2 = torch.zeros((H, W, 4), device=dev)
+    if w.display:
+        assert V == 1, "display workloads are single-view"
+        DW, DH = w.display
+        sky = torch.tensor(scenes.sky_background(DW, DH), device=dev)
+        frame_out = torch.empty((DH, DW, 4), device=dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
 
     def frame(f, events=None):
+        resolve(f, events)
+        if w.display:
+            resolved = hist[0] if not reproject or f % 2 == 1 else hist2
+            cf.cloud_composite(resolved, sky, out=frame_out)
+
+    def resolve(f, events=None):
         if events:
             events[0].record()
         if reproject:
@@ -524,11 +611,13 @@ def main():
         "data": "synthetic: seeded 5-octave value-noise FBM density 256^3 "
                 f"({args.dtype} storage, {args.layout} layout), orbiting camera",
         "config": {"workload": f"{w.name}: {w.description}", "width": W, "height": H,
+                   "display": list(w.display) or None,
                    "primary_steps": p.steps, "light_steps": p.light_steps, "jitter": JITTER_NAMES[p.jitter],
                    "integration": "analytic", "taa_blend": w.taa_blend, "taa": args.taa,
                    "volume": f"{w.volume.n}^3 {args.dtype}", "layout": args.layout,
                    "occupancy_skip": not args.no_occupancy,
-                   "lookups_per_frame": round(lk_frame)},
+                   "lookups_per_frame": round(lk_frame),
+                   "nominal_lookups_per_frame": V * W * H * p.steps * (1 + p.light_steps)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": MI355X_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / MI355X_HBM_GBPS, 4),
                      "traffic": recorded_traffic(traffic_key), "kernel": "render_kernel",

@@ -235,6 +235,21 @@ int cloud_taa_resolve_reproject(const float* current, const float* depth,
                                 int32_t width, int32_t height, float blend,
                                 uint32_t frame_index, void* hip_stream);
 
+/* Composites a resolved cloud layer into the scene (Section 3.2: the
+ * clouds are rendered and resolved in a low-resolution buffer, then
+ * composited into the rest of the frame). The layer (premultiplied RGBA,
+ * cloud_width x cloud_height) is up-sampled bilinearly to width x height with
+ * pixel centres aligned -- output pixel x samples the layer at
+ * (x + 1/2) * cloud_width / width - 1/2, likewise in y, edge-clamped -- then
+ * out = c + (1 - c.alpha) * background in every channel.
+ *  cloud                device [cloud_height][cloud_width][4] float32.
+ *  background, out      device [height][width][4] float32.
+ * All 16-byte aligned. out may be background itself (in place) but must not
+ * overlap it otherwise, nor overlap cloud. */
+int cloud_composite(const float* cloud, int32_t cloud_width, int32_t cloud_height,
+                    const float* background, float* out, int32_t width,
+                    int32_t height, void* hip_stream);
+
 /* Adds to *out_count (device, one uint64, 8-byte aligned) the number of
  * trilinear density lookups cloud_render performs for this frame: one per
  * primary sample taken plus light_steps per sample with non-zero density,

@@ -32,6 +32,20 @@ the function that applies it):
 * R14 The random offset is a PCG hash chain (Jarzynski and Olano 2020) of the
       pixel, frame and seed, so the library and the oracle draw the same j.
 * R16 Pinhole camera, vertical field of view, pixel centres, row 0 at the top.
+* R17 Coherent jitter variants (Section 5 leaves cheaper jitter to future
+      work; Section 4 reports that one offset for every ray of a frame
+      removes the cost but defeats the resolve): one offset per 8x8-pixel
+      tile (the hash of (px >> 3, py >> 3)) and one per frame (of (0, 0)).
+* R18 Reprojected resolve (Playdead's TAA, Section 3.2, reprojects its
+      history): a ray's representative depth is its mean sample distance
+      weighted by the opacity each step adds, where alpha >= 0.01; the middle
+      of its chord through the box below that; at infinity for a miss. The
+      point there is projected into the previous camera, the history sampled
+      bilinearly (edge clamp), then clamped and blended as in R13; a point
+      behind the previous camera or off its image takes the current value.
+* R19 Composite (Section 3.2): the resolved low-resolution layer is
+      up-sampled bilinearly with pixel centres aligned (edge clamp) and laid
+      over the scene with the premultiplied over operator.
 """
 
 from __future__ import annotations

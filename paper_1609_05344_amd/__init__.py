@@ -20,6 +20,7 @@ from ._lib import (  # noqa: F401
     cloud_render_views,
     cloud_render_depth,
     cloud_taa_resolve_reproject,
+    cloud_composite,
     cloud_taa_resolve,
     cloud_tune,
     cloud_volume_occupancy,

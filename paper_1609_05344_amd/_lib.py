@@ -97,6 +97,8 @@ def load():
     lib.cloud_taa_resolve_reproject.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p,
                                                 POINTER(cloud_camera), POINTER(cloud_camera),
                                                 c_int32, c_int32, c_float, c_uint32, c_void_p]
+    lib.cloud_composite.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32,
+                                    c_int32, c_void_p]
     lib.cloud_lookup_trace.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,
                                        POINTER(cloud_params), c_uint32, c_int32, c_int32,
                                        c_void_p, c_void_p]
@@ -109,7 +111,7 @@ def load():
     for name in ("cloud_render", "cloud_render_views", "cloud_march_rays", "cloud_taa_resolve",
                  "cloud_jitter_offsets", "cloud_check_buffer", "cloud_count_lookups",
                  "cloud_lookup_trace", "cloud_gather_ceiling", "cloud_render_depth",
-                 "cloud_taa_resolve_reproject",
+                 "cloud_taa_resolve_reproject", "cloud_composite",
                  "cloud_volume_packed_bytes", "cloud_volume_pack", "cloud_tune"):
         getattr(lib, name).restype = c_int
     _lib = lib
@@ -282,6 +284,17 @@ def cloud_taa_resolve_reproject(current, depth, history, out, camera, prev_camer
                                              ctypes.byref(cam), ctypes.byref(prev), W, H,
                                              float(blend), int(frame_index) & 0xFFFFFFFF,
                                              _stream(stream)))
+    return out
+
+
+def cloud_composite(cloud, background, out=None, stream=None):
+    """Up-sample the cloud layer [h, w, 4] to the background's size and
+    composite it over the background; returns out [H, W, 4]."""
+    lh, lw = int(cloud.shape[0]), int(cloud.shape[1])
+    H, W = int(background.shape[0]), int(background.shape[1])
+    out = _out(out, (H, W, 4), background.device)
+    check(load().cloud_composite(_ptr(cloud), lw, lh, _ptr(background), _ptr(out), W, H,
+                                 _stream(stream)))
     return out
 
 

@@ -599,6 +599,31 @@ int cloud_taa_resolve_reproject(const float* current, const float* depth, const 
   CLOUD_GUARD_END
 }
 
+int cloud_composite(const float* cloud, int32_t cloud_width, int32_t cloud_height,
+                    const float* background, float* out, int32_t width, int32_t height,
+                    void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  int rc = check_image(width, height, 1);
+  if (rc) return rc;
+  if ((rc = check_image(cloud_width, cloud_height, 1))) return rc;
+  const size_t lbytes = (size_t)cloud_width * cloud_height * 16, bytes = (size_t)width * height * 16;
+  if ((rc = check_span(cloud, lbytes, "cloud"))) return rc;
+  if ((rc = check_span(background, bytes, "background"))) return rc;
+  if ((rc = check_span(out, bytes, "out"))) return rc;
+  const uintptr_t c = reinterpret_cast<uintptr_t>(cloud), b = reinterpret_cast<uintptr_t>(background),
+                  o = reinterpret_cast<uintptr_t>(out);
+  if ((c | b | o) % 16) return fail(CLOUD_E_INVALID, "images must be 16-byte aligned");
+  if (c < o + bytes && o < c + lbytes) return fail(CLOUD_E_INVALID, "out overlaps cloud");
+  if (b != o && b < o + bytes && o < b + bytes)
+    return fail(CLOUD_E_INVALID, "out partially overlaps background");
+  hipError_t e = launch_composite(cloud, cloud_width, cloud_height, background, out, width, height,
+                                  static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("composite launch: ") + hipGetErrorString(e));
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
 int cloud_volume_occupancy_bytes(const cloud_volume* dense, uint64_t* bytes, int32_t* log2_brick) {
   CLOUD_GUARD_BEGIN
   clear_error();

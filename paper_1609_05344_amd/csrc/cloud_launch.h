@@ -37,6 +37,10 @@ hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevPar
                          float* out, unsigned long long* counts, uint32_t* trace,
                          float* depth, hipStream_t s);
 
+// Up-sample the lw x lh layer to W x H and composite it over bg into out.
+hipError_t launch_composite(const float* layer, int lw, int lh, const float* bg, float* out, int W,
+                            int H, hipStream_t s);
+
 // Temporal resolve with camera reprojection (out must not alias hist).
 hipError_t launch_taa_reproject(const float* cur, const float* depth, const float* hist,
                                 float* out, const DevCamera& cam, const DevCamera& prev, int W,

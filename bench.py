@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_HBM_GBPS = 8000.0
+# FP32 vector issue peak without packed math: 256 CUs x 64 lanes x 2.4 GHz
+MI355X_VALU_LANE_INSTR_PER_S = 256 * 64 * 2.4e9
 MI355X_FP32_VECTOR_TFLOPS = 157.3
 KERNEL_SOURCES = ["cloud_device.h", "cloud_types.h", "render.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
@@ -47,17 +49,22 @@ def kernel_source_sha1() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(config: dict):
-    """HBM bytes per render launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE measurement, or None when the kernel or config differ."""
+def recorded_counters(config: dict) -> dict:
+    """The committed rocprofv3 measurement of the render kernel (HBM bytes per
+    launch from FETCH_SIZE / WRITE_SIZE, VALU instructions per launch from
+    SQ_INSTS_VALU), or {} when the kernel sources or the config differ."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if rec.get("source_sha1") != kernel_source_sha1() or rec.get("config") != config:
-        return None
-    return rec.get("traffic_bytes_per_launch")
+        return {}
+    return rec
+
+
+def recorded_traffic(config: dict):
+    return recorded_counters(config).get("traffic_bytes_per_launch")
 
 
 # ---------------------------------------------------------------------------
@@ -101,6 +108,19 @@ def cpu_baseline(name: str, dtype: str, frames: int, cores: int) -> dict:
                       f"({lookups} executed lookups, {dt:.1f} s wall), FP64 numpy, "
                       f"{cores} processes over row bands",
             "ms_per_frame": round(dt * 1e3 / frames, 1)}
+
+
+def valu_fraction(rec: dict, render_ms: float):
+    """Wave-level VALU instructions per launch (SQ_INSTS_VALU) x 64 lanes over
+    the render's duration, against the non-packed FP32 issue peak."""
+    n = rec.get("valu_insts_per_launch")
+    if not n:
+        return None
+    rate = n * 64 / (render_ms * 1e-3)
+    return {"lane_instr_per_s": round(rate / 1e12, 3), "unit": "T lane-instr/s",
+            "peak": round(MI355X_VALU_LANE_INSTR_PER_S / 1e12, 2),
+            "frac": round(rate / MI355X_VALU_LANE_INSTR_PER_S, 4),
+            "insts_per_launch": n}
 
 
 # ---------------------------------------------------------------------------
@@ -621,6 +641,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": MI355X_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / MI355X_HBM_GBPS, 4),
                      "traffic": recorded_traffic(traffic_key), "kernel": "render_kernel",
+                     "valu": valu_fraction(recorded_counters(traffic_key), render_ms),
                      "kernel_ms": round(render_ms, 4),
                      "algorithmic_bytes_per_launch": round(lk_frame * bytes_per_lookup),
                      "bytes_per_lookup": bytes_per_lookup,

@@ -57,11 +57,14 @@ enum {
  * replicate each trilinear footprint so that a lookup is one or two aligned
  * fetches instead of eight scattered ones (see cloud_volume_pack).
  *  DENSE  [nz][ny][nx] texels.
- *  QUAD   [nz][ny+1][nx+1] entries of 4 texels: entry (z, y', x') holds the
- *         texels (x, y), (x+1, y), (x, y+1), (x+1, y+1) of plane z with
+ *  QUAD   nz x (ny+1) x (nx+1) entries of 4 texels: entry (z, y', x') holds
+ *         the texels (x, y), (x+1, y), (x, y+1), (x+1, y+1) of plane z with
  *         x = x'-1, y = y'-1, indices clamped to the volume (4x storage).
- *  OCT    [nz+1][ny+1][nx+1] entries of 8 texels: the QUAD entry of plane
- *         z'-1 then that of plane z' (planes clamped; 8x storage). */
+ *  OCT    (nz+1) x (ny+1) x (nx+1) entries of 8 texels: the QUAD entry of
+ *         plane z'-1 then that of plane z' (planes clamped; 8x storage).
+ * Packed entries are stored in bricks of 2 x 2 x 2 (x fastest inside a
+ * brick, then y, then z), bricks in [z][y][x] order, each axis rounded up
+ * to an even count; cloud_volume_packed_bytes gives the size. */
 enum { CLOUD_LAYOUT_DENSE = 0, CLOUD_LAYOUT_QUAD = 1, CLOUD_LAYOUT_OCT = 2 };
 
 /* Storage type of a density volume. Every type is decoded exactly to

@@ -71,9 +71,11 @@ int volume_layout_bytes(const cloud_volume* v, int layout, size_t* bytes) {
   const long long ey = layout == CLOUD_LAYOUT_DENSE ? v->ny : (long long)v->ny + 1;
   const long long ez = layout == CLOUD_LAYOUT_OCT ? (long long)v->nz + 1 : v->nz;
   if (ex * ey >= (1LL << 24)) return fail(CLOUD_E_INVALID, "volume planes must hold < 2^24 texels");
-  if (ex * ey * ez > 0x7FFFFFFFLL) return fail(CLOUD_E_INVALID, "volume has too many texels");
+  long long row, plane, entries = ex * ey * ez;
+  if (layout != CLOUD_LAYOUT_DENSE) packed_strides(ex, ey, ez, &row, &plane, &entries);
+  if (entries > 0x7FFFFFFFLL) return fail(CLOUD_E_INVALID, "volume has too many texels");
   const int corners = layout == CLOUD_LAYOUT_DENSE ? 1 : layout == CLOUD_LAYOUT_QUAD ? 4 : 8;
-  *bytes = (size_t)(ex * ey * ez) * corners * dtype_size(v->dtype);
+  *bytes = (size_t)entries * corners * dtype_size(v->dtype);
   return CLOUD_OK;
 }
 
@@ -114,8 +116,16 @@ int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
   DevVolume d = {};
   d.base = v->base;
   d.nx = v->nx; d.ny = v->ny; d.nz = v->nz;
-  d.row = v->layout == CLOUD_LAYOUT_DENSE ? v->nx : v->nx + 1;
-  d.plane = d.row * (v->layout == CLOUD_LAYOUT_DENSE ? v->ny : v->ny + 1);
+  if (v->layout == CLOUD_LAYOUT_DENSE) {
+    d.row = v->nx;
+    d.plane = v->nx * v->ny;
+  } else {
+    long long row, plane, entries;
+    packed_strides(v->nx + 1, v->ny + 1, v->layout == CLOUD_LAYOUT_OCT ? v->nz + 1 : v->nz, &row,
+                   &plane, &entries);
+    d.row = (int)row;
+    d.plane = (int)plane;
+  }
   const int n[3] = {v->nx, v->ny, v->nz};
   float* s[3] = {&d.sx, &d.sy, &d.sz};
   float* o[3] = {&d.ox, &d.oy, &d.oz};

@@ -182,9 +182,10 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
   }
 };
 
-// Entry of corner k (in [-1, n-1] per axis) of a packed volume.
-__device__ __forceinline__ int packed_xy(const DevVolume& v, int kx, int ky) {
-  return __umul24(min(ky, v.ny - 1) + 1, v.row) + min(kx, v.nx - 1) + 1;
+// Entry of the footprint with corner k (kx, ky in [-1, n-1]) in packed plane
+// z of a packed volume.
+__device__ __forceinline__ int packed_entry(const DevVolume& v, int kx, int ky, int z) {
+  return packed_index(min(kx, v.nx - 1) + 1, min(ky, v.ny - 1) + 1, z, v.row, v.plane);
 }
 
 // Four float32 texels, or eight 16-bit texels packed two to a word (low half
@@ -208,10 +209,10 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
-    const int e = packed_xy(v, kx, ky);
     const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
-    const int ea = live ? __umul24(za, v.plane) + e : 0;
-    const int eb = live ? __umul24(zb, v.plane) + e : 0;
+    const int ia = packed_entry(v, kx, ky, za), ib = packed_entry(v, kx, ky, zb);
+    const int ea = live ? ia : 0;
+    const int eb = live ? ib : 0;
     if constexpr (DT == DT_F32) {
       const uint4* q = static_cast<const uint4*>(v.base);
       const uint4 A = q[ea], B = q[eb];
@@ -236,7 +237,8 @@ struct BaseSampler<DT, LAYOUT_OCT> {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
-    const int e = live ? __umul24(min(kz, v.nz - 1) + 1, v.plane) + packed_xy(v, kx, ky) : 0;
+    const int ie = packed_entry(v, kx, ky, min(kz, v.nz - 1) + 1);
+    const int e = live ? ie : 0;
     if constexpr (DT == DT_F32) {
       const uint4* q = static_cast<const uint4*>(v.base) + 2 * (size_t)e;
       const uint4 A = q[0], B = q[1];

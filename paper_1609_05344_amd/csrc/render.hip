@@ -109,18 +109,20 @@ __global__ __launch_bounds__(256) void rays_kernel(DevVolume vol, DevParams prm,
 
 template <typename E, int CORNERS>
 __global__ __launch_bounds__(256) void pack_kernel(const E* __restrict__ src, int nx, int ny,
-                                                   int nz, int ez, E* __restrict__ dst) {
+                                                   int nz, int ez, int row, int plane,
+                                                   E* __restrict__ dst) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long ex = nx + 1, ey = ny + 1;
   if (e >= ex * ey * ez) return;
-  const int x = (int)(e % ex) - 1;
-  const int y = (int)((e / ex) % ey) - 1;
-  const int z = (int)(e / (ex * ey)) - (CORNERS == 8 ? 1 : 0);
+  const int ix = (int)(e % ex), iy = (int)((e / ex) % ey), iz = (int)(e / (ex * ey));
+  const int x = ix - 1;
+  const int y = iy - 1;
+  const int z = iz - (CORNERS == 8 ? 1 : 0);
   const int xa = min(max(x, 0), nx - 1), xb = min(max(x + 1, 0), nx - 1);
   const int ya = min(max(y, 0), ny - 1), yb = min(max(y + 1, 0), ny - 1);
   const int za = min(max(z, 0), nz - 1), zb = min(max(z + 1, 0), nz - 1);
   const size_t pa = (size_t)za * ny * nx, pb = (size_t)zb * ny * nx;
-  E* o = dst + (size_t)e * CORNERS;
+  E* o = dst + (size_t)packed_index(ix, iy, iz, row, plane) * CORNERS;
   o[0] = src[pa + (size_t)ya * nx + xa];
   o[1] = src[pa + (size_t)ya * nx + xb];
   o[2] = src[pa + (size_t)yb * nx + xa];
@@ -377,20 +379,26 @@ hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, 
   const int ez = layout == LAYOUT_OCT ? nz + 1 : nz;
   const long long entries = (long long)(nx + 1) * (ny + 1) * ez;
   const unsigned blocks = (unsigned)((entries + 255) / 256);
+  long long row, plane, stored;
+  packed_strides(nx + 1, ny + 1, ez, &row, &plane, &stored);
   if (elem_bytes == 4) {
     if (layout == LAYOUT_OCT)
       hipLaunchKernelGGL((pack_kernel<uint32_t, 8>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, static_cast<uint32_t*>(dst));
+                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, (int)row, (int)plane,
+                         static_cast<uint32_t*>(dst));
     else
       hipLaunchKernelGGL((pack_kernel<uint32_t, 4>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, static_cast<uint32_t*>(dst));
+                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, (int)row, (int)plane,
+                         static_cast<uint32_t*>(dst));
   } else {
     if (layout == LAYOUT_OCT)
       hipLaunchKernelGGL((pack_kernel<uint16_t, 8>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, static_cast<uint16_t*>(dst));
+                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, (int)row, (int)plane,
+                         static_cast<uint16_t*>(dst));
     else
       hipLaunchKernelGGL((pack_kernel<uint16_t, 4>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, static_cast<uint16_t*>(dst));
+                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, (int)row, (int)plane,
+                         static_cast<uint16_t*>(dst));
   }
   return hipGetLastError();
 }

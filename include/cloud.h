@@ -62,9 +62,13 @@ enum {
  *         x = x'-1, y = y'-1, indices clamped to the volume (4x storage).
  *  OCT    (nz+1) x (ny+1) x (nx+1) entries of 8 texels: the QUAD entry of
  *         plane z'-1 then that of plane z' (planes clamped; 8x storage).
- * Packed entries are stored in bricks of 2 x 2 x 2 (x fastest inside a
- * brick, then y, then z), bricks in [z][y][x] order, each axis rounded up
- * to an even count; cloud_volume_packed_bytes gives the size. */
+ * Packed entries are stored in bricks of 8 entries (one 128-byte line of
+ * 16-byte entries): 2^bx x 2^by x 2^bz entries with (bx, by, bz) from
+ * cloud_volume.brick_log2 (default 1, 1, 1), x fastest inside a brick, then
+ * y, then z, bricks in [z][y][x] order, each axis rounded up to whole bricks;
+ * cloud_volume_packed_bytes gives the size. The brick shape changes only
+ * addresses (renders are bitwise the same); the best shape depends on the
+ * workload. */
 enum { CLOUD_LAYOUT_DENSE = 0, CLOUD_LAYOUT_QUAD = 1, CLOUD_LAYOUT_OCT = 2 };
 
 /* Storage type of a density volume. Every type is decoded exactly to
@@ -92,6 +96,10 @@ enum { CLOUD_F32 = 0, CLOUD_F16 = 1, CLOUD_BF16 = 2 };
  *          starting in that brick can touch is zero. A lookup in a clear
  *          brick is exactly zero, so it is answered without reading the
  *          volume; results are bitwise identical with and without it.
+ *  brick_log2      packed layouts: log2 of the brick extent along x, y, z,
+ *          each in [0, 3] and summing to 3, or all 0 for (1, 1, 1). A packed
+ *          volume must be described with the shape it was packed with
+ *          (cloud_volume_pack copies it into the packed descriptor).
  *  Requirements: n* >= 2, dn* >= 2 when detail is set, fewer than 2^24
  *  entries per plane, box_max > box_min on every axis,
  *  0 <= detail_weight < 1, detail_tiling > 0, detail values in [0, 1].
@@ -110,6 +118,7 @@ typedef struct {
   int32_t layout;
   const uint32_t* occupancy;
   int32_t occupancy_log2;
+  int32_t brick_log2[3];  /* packed layouts: brick shape (see above); all 0 = 1, 1, 1 */
 } cloud_volume;
 
 /* Pinhole camera: rays leave pos through pixel centres; vfov_deg is the
@@ -326,10 +335,10 @@ int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t ds
  * its 16x16-pixel tiles in S x S super-tiles so that the tiles an XCD works on
  * together cover a compact patch of the image (0 = row-major); "taa_tile"
  * (16, 32 or 64, default 32) -- the resolve's tile width in pixels (each
- * tile holds 256 pixels); "render_blocks_per_cu" -- at most this many render
- * workgroups resident per CU, enforced by reserving LDS at launch
- * (CLOUD_E_INVALID when the device's LDS cannot express it); 0 = no cap;
- * -1 (default) = 3 for float32 quad/oct volumes, no cap otherwise. */
+ * tile holds 256 pixels); "render_blocks_per_cu" (0..64, default 0 = no cap)
+ * -- at most this many render workgroups resident per CU, enforced by
+ * reserving LDS at launch (CLOUD_E_INVALID when the device's LDS cannot
+ * express it). */
 int cloud_tune(const char* key, int32_t value);
 
 /* Checks that [ptr, ptr + bytes) lies inside one HIP device allocation: the

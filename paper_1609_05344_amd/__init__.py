@@ -31,9 +31,11 @@ from ._lib import (  # noqa: F401
 )
 
 
-def device_volume(scene, device="cuda", layout: str = "dense", occupancy: bool = False):
+def device_volume(scene, device="cuda", layout: str = "dense", occupancy: bool = False,
+                  brick=None):
     """Upload a seeded scene's stored volumes (see scenes.make_scene),
-    optionally with an occupancy bitmap and in a packed layout."""
+    optionally with an occupancy bitmap and in a packed layout (entries in
+    bricks of shape `brick`, log2 per axis; None for the default)."""
     import numpy as np
     import torch
 
@@ -54,5 +56,5 @@ def device_volume(scene, device="cuda", layout: str = "dense", occupancy: bool =
     if occupancy:
         vol = cloud_volume_occupancy(vol)
     if layout != "dense":
-        vol = cloud_volume_pack(vol, layout)
+        vol = cloud_volume_pack(vol, layout, brick=brick)
     return vol

@@ -39,7 +39,7 @@ class cloud_volume(ctypes.Structure):
         ("detail", c_void_p), ("dnx", c_int32), ("dny", c_int32), ("dnz", c_int32),
         ("ddtype", c_int32), ("detail_weight", c_float), ("detail_tiling", c_float),
         ("box_min", c_float * 3), ("box_max", c_float * 3), ("layout", c_int32),
-        ("occupancy", c_void_p), ("occupancy_log2", c_int32),
+        ("occupancy", c_void_p), ("occupancy_log2", c_int32), ("brick_log2", c_int32 * 3),
     ]
 
 
@@ -328,21 +328,33 @@ def cloud_gather_ceiling(volume: Volume, cameras, params, frame_index: int, widt
     return out
 
 
-def cloud_volume_packed_bytes(volume: Volume, layout: str) -> int:
+def _struct_with_brick(volume: Volume, brick):
+    st = cloud_volume()
+    ctypes.memmove(ctypes.byref(st), ctypes.byref(volume.struct), ctypes.sizeof(cloud_volume))
+    if brick is not None:
+        st.brick_log2[:] = [int(b) for b in brick]
+    return st
+
+
+def cloud_volume_packed_bytes(volume: Volume, layout: str, brick=None) -> int:
+    """Bytes of a packed copy; brick: (bx, by, bz) log2 brick shape, or None
+    for the default."""
     n = c_uint64(0)
-    check(load().cloud_volume_packed_bytes(ctypes.byref(volume.struct), LAYOUTS[layout],
-                                           ctypes.byref(n)))
+    st = _struct_with_brick(volume, brick)
+    check(load().cloud_volume_packed_bytes(ctypes.byref(st), LAYOUTS[layout], ctypes.byref(n)))
     return int(n.value)
 
 
-def cloud_volume_pack(volume: Volume, layout: str, stream=None) -> "Volume":
+def cloud_volume_pack(volume: Volume, layout: str, stream=None, brick=None) -> "Volume":
     """Packed copy of a dense volume (a new device buffer owned by the returned
-    Volume)."""
+    Volume); brick: (bx, by, bz) log2 brick shape of the packed entries, or
+    None for the default (1, 1, 1)."""
     import torch
-    nbytes = cloud_volume_packed_bytes(volume, layout)
+    nbytes = cloud_volume_packed_bytes(volume, layout, brick)
     buf = torch.empty((nbytes,), dtype=torch.uint8, device=volume.base.device)
     packed = cloud_volume()
-    check(load().cloud_volume_pack(ctypes.byref(volume.struct), LAYOUTS[layout], _ptr(buf), nbytes,
+    st = _struct_with_brick(volume, brick)
+    check(load().cloud_volume_pack(ctypes.byref(st), LAYOUTS[layout], _ptr(buf), nbytes,
                                    ctypes.byref(packed), _stream(stream)))
     out = Volume.__new__(Volume)
     out.base, out.detail, out.dtype = buf, volume.detail, volume.dtype

@@ -60,6 +60,21 @@ int check_image(int W, int H, long long views) {
   return CLOUD_OK;
 }
 
+// Brick shifts of a volume's packed entries (all zero means 1, 1, 1); false
+// when the shape is not one of 8 entries with every shift in [0, 3].
+bool brick_shape(const cloud_volume* v, int b[3]) {
+  const int* s = v->brick_log2;
+  if (s[0] == 0 && s[1] == 0 && s[2] == 0) {
+    b[0] = b[1] = b[2] = 1;
+    return true;
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (s[k] < 0 || s[k] > 3) return false;
+    b[k] = s[k];
+  }
+  return b[0] + b[1] + b[2] == 3;
+}
+
 int volume_layout_bytes(const cloud_volume* v, int layout, size_t* bytes) {
   if (!v) return fail(CLOUD_E_INVALID, "volume is NULL");
   if (layout < CLOUD_LAYOUT_DENSE || layout > CLOUD_LAYOUT_OCT)
@@ -72,7 +87,12 @@ int volume_layout_bytes(const cloud_volume* v, int layout, size_t* bytes) {
   const long long ez = layout == CLOUD_LAYOUT_OCT ? (long long)v->nz + 1 : v->nz;
   if (ex * ey >= (1LL << 24)) return fail(CLOUD_E_INVALID, "volume planes must hold < 2^24 texels");
   long long row, plane, entries = ex * ey * ez;
-  if (layout != CLOUD_LAYOUT_DENSE) packed_strides(ex, ey, ez, &row, &plane, &entries);
+  if (layout != CLOUD_LAYOUT_DENSE) {
+    int b[3];
+    if (!brick_shape(v, b))
+      return fail(CLOUD_E_INVALID, "brick_log2 must be three shifts in [0, 3] summing to 3, or all 0");
+    packed_strides(ex, ey, ez, b[0], b[1], b[2], &row, &plane, &entries);
+  }
   if (entries > 0x7FFFFFFFLL) return fail(CLOUD_E_INVALID, "volume has too many texels");
   const int corners = layout == CLOUD_LAYOUT_DENSE ? 1 : layout == CLOUD_LAYOUT_QUAD ? 4 : 8;
   *bytes = (size_t)entries * corners * dtype_size(v->dtype);
@@ -120,11 +140,16 @@ int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
     d.row = v->nx;
     d.plane = v->nx * v->ny;
   } else {
+    int b[3];
+    brick_shape(v, b);   // validated by volume_layout_bytes
     long long row, plane, entries;
-    packed_strides(v->nx + 1, v->ny + 1, v->layout == CLOUD_LAYOUT_OCT ? v->nz + 1 : v->nz, &row,
-                   &plane, &entries);
+    packed_strides(v->nx + 1, v->ny + 1, v->layout == CLOUD_LAYOUT_OCT ? v->nz + 1 : v->nz, b[0],
+                   b[1], b[2], &row, &plane, &entries);
     d.row = (int)row;
     d.plane = (int)plane;
+    d.bx = b[0];
+    d.by = b[1];
+    d.bz = b[2];
   }
   const int n[3] = {v->nx, v->ny, v->nz};
   float* s[3] = {&d.sx, &d.sy, &d.sz};
@@ -478,7 +503,10 @@ int cloud_volume_pack(const cloud_volume* dense, int32_t layout, void* dst, uint
     if (d0 < t0 + tbytes && t0 < d0 + need) return fail(CLOUD_E_INVALID, "dst overlaps the detail volume");
   }
   const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  hipError_t e = launch_pack(dense->base, (int)es, dense->nx, dense->ny, dense->nz, layout, dst, s);
+  int brick[3];
+  brick_shape(dense, brick);   // validated by packed_bytes
+  hipError_t e = launch_pack(dense->base, (int)es, dense->nx, dense->ny, dense->nz, layout, brick,
+                             dst, s);
   if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("pack launch: ") + hipGetErrorString(e));
   void* ddst = nullptr;
   if (dense->detail) {
@@ -489,6 +517,7 @@ int cloud_volume_pack(const cloud_volume* dense, int32_t layout, void* dst, uint
   *packed = *dense;
   packed->base = dst;
   packed->layout = layout;
+  for (int k = 0; k < 3; ++k) packed->brick_log2[k] = brick[k];
   if (dense->detail) packed->detail = ddst;
   return CLOUD_OK;
   CLOUD_GUARD_END
@@ -697,8 +726,7 @@ int cloud_tune(const char* key, int32_t value) {
     return CLOUD_OK;
   }
   if (k == "render_blocks_per_cu") {
-    if (value < -1 || value > 64)
-      return fail(CLOUD_E_INVALID, "render_blocks_per_cu must be -1 (automatic) or in [0, 64]");
+    if (value < 0 || value > 64) return fail(CLOUD_E_INVALID, "render_blocks_per_cu must be in [0, 64]");
     if (value > 0 && residency_lds(value, 4096) < 0)
       return fail(CLOUD_E_INVALID, "render_blocks_per_cu: this cap cannot be set through LDS");
     tuning().render_blocks_per_cu = value;

@@ -185,7 +185,8 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
 // Entry of the footprint with corner k (kx, ky in [-1, n-1]) in packed plane
 // z of a packed volume.
 __device__ __forceinline__ int packed_entry(const DevVolume& v, int kx, int ky, int z) {
-  return packed_index(min(kx, v.nx - 1) + 1, min(ky, v.ny - 1) + 1, z, v.row, v.plane);
+  return packed_index(min(kx, v.nx - 1) + 1, min(ky, v.ny - 1) + 1, z, v.bx, v.by, v.bz, v.row,
+                      v.plane);
 }
 
 // Four float32 texels, or eight 16-bit texels packed two to a word (low half

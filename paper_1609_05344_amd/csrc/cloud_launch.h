@@ -11,10 +11,9 @@ namespace cloud {
 struct Tuning {
   int supertile = 4;   // render tile walk: S x S super-tiles (0 = row-major)
   int taa_tile = 32;   // resolve tile width in pixels (16, 32 or 64; 256 pixels a tile)
-  // cap on resident render workgroups per CU: 0 none, -1 automatic (3 for
-  // float32 packed volumes, whose two fetches per lookup thrash the caches
-  // when more rays are in flight; none otherwise)
-  int render_blocks_per_cu = -1;
+  // cap on resident render workgroups per CU (0: none, the default; with the
+  // bricked packed layouts every measured cap was slower)
+  int render_blocks_per_cu = 0;
 };
 Tuning& tuning();
 
@@ -59,9 +58,9 @@ hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParam
                        long long n, float* out, hipStream_t s);
 
 // Pack a dense [nz][ny][nx] volume of 2- or 4-byte texels into a quad or oct
-// layout at dst.
+// layout at dst, entries in bricks of brick[0..2] (log2 per axis).
 hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,
-                       void* dst, hipStream_t s);
+                       const int* brick, void* dst, hipStream_t s);
 
 // Pack a dense repeat-addressed detail volume into its oct-wrap layout.
 hipError_t launch_pack_detail(const void* src, int elem_bytes, int nx, int ny, int nz, void* dst,

@@ -17,14 +17,12 @@ constexpr int kMaxViews = 16;   // cameras carried by value in one launch
 // replicate each lookup's footprint so that it is one aligned fetch.
 enum { LAYOUT_DENSE = 0, LAYOUT_QUAD = 1, LAYOUT_OCT = 2 };
 
-// Entry order of the packed layouts: 1 (default) bricks of 2x2x2 entries --
-// one 128-byte line of 16-byte entries -- with the bricks row-major, so that a
-// line holds a small cube of footprints and a quad lookup's two planes share
-// a line half the time; 0 row-major [z][y][x] entries. Renders are bitwise the
-// same either way; only the addresses differ.
-#ifndef CLOUD_SWIZZLE
-#define CLOUD_SWIZZLE 1
-#endif
+// Entry order of the packed layouts: bricks of 2^bx x 2^by x 2^bz entries --
+// 8 in all, one 128-byte line of 16-byte entries -- x fastest inside a brick,
+// then y, then z, with the bricks themselves row-major. The shape is a
+// property of the packed volume (default 2 x 2 x 2: a small cube of
+// footprints per line, and a quad lookup's two planes share a line half the
+// time). Renders are bitwise the same for every shape; only addresses differ.
 
 // Product of two non-negative ints below 2^24 (plane strides are checked
 // against that on the host): the full-rate 24-bit multiply on the device.
@@ -36,31 +34,25 @@ inline __host__ __device__ int mul24(int a, int b) {
 #endif
 }
 
-// Index of packed entry (x, y, z) given the row and plane strides (entries
-// per row and per plane, or bricks per brick row and brick plane).
-inline __host__ __device__ int packed_index(int x, int y, int z, int row, int plane) {
-#if CLOUD_SWIZZLE
-  return ((mul24(z >> 1, plane) + mul24(y >> 1, row) + (x >> 1)) << 3) | ((z & 1) << 2) |
-         ((y & 1) << 1) | (x & 1);
-#else
-  return mul24(z, plane) + mul24(y, row) + x;
-#endif
+// Index of packed entry (x, y, z) for brick shifts (bx, by, bz) and the
+// brick-row and brick-plane strides.
+inline __host__ __device__ int packed_index(int x, int y, int z, int bx, int by, int bz, int row,
+                                            int plane) {
+  return ((mul24(z >> bz, plane) + mul24(y >> by, row) + (x >> bx)) << 3) |
+         ((z & ((1 << bz) - 1)) << (bx + by)) | ((y & ((1 << by) - 1)) << bx) |
+         (x & ((1 << bx) - 1));
 }
 
-// Strides and entry count of a packed layout of ex x ey x ez entries.
-inline __host__ __device__ void packed_strides(long long ex, long long ey, long long ez,
-                                               long long* row, long long* plane,
+// Strides (bricks per brick row and per brick plane) and the stored entry
+// count of a packed layout of ex x ey x ez entries in bricks (bx, by, bz).
+inline __host__ __device__ void packed_strides(long long ex, long long ey, long long ez, int bx,
+                                               int by, int bz, long long* row, long long* plane,
                                                long long* entries) {
-#if CLOUD_SWIZZLE
-  const long long bx = (ex + 1) / 2, by = (ey + 1) / 2, bz = (ez + 1) / 2;
-  *row = bx;
-  *plane = bx * by;
-  *entries = bx * by * bz * 8;
-#else
-  *row = ex;
-  *plane = ex * ey;
-  *entries = ex * ey * ez;
-#endif
+  const long long nbx = (ex + (1 << bx) - 1) >> bx, nby = (ey + (1 << by) - 1) >> by;
+  const long long nbz = (ez + (1 << bz) - 1) >> bz;
+  *row = nbx;
+  *plane = nbx * nby;
+  *entries = nbx * nby * nbz * 8;
 }
 
 struct DevVolume {
@@ -68,6 +60,7 @@ struct DevVolume {
   int nx, ny, nz;
   int plane;            // dense: nx * ny; packed: the plane stride of packed_index
   int row;              // dense: nx; packed: the row stride of packed_index
+  int bx, by, bz;       // packed: brick shifts of packed_index
   // continuous texel coordinate along each axis: f = p * s + o, texel k's
   // centre at f = k (texel centres at box_min + (k + 0.5) * extent / n)
   float sx, sy, sz, ox, oy, oz;

@@ -109,8 +109,8 @@ __global__ __launch_bounds__(256) void rays_kernel(DevVolume vol, DevParams prm,
 
 template <typename E, int CORNERS>
 __global__ __launch_bounds__(256) void pack_kernel(const E* __restrict__ src, int nx, int ny,
-                                                   int nz, int ez, int row, int plane,
-                                                   E* __restrict__ dst) {
+                                                   int nz, int ez, int bx, int by, int bz,
+                                                   int row, int plane, E* __restrict__ dst) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long ex = nx + 1, ey = ny + 1;
   if (e >= ex * ey * ez) return;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const E* __restrict__ src, in
   const int ya = min(max(y, 0), ny - 1), yb = min(max(y + 1, 0), ny - 1);
   const int za = min(max(z, 0), nz - 1), zb = min(max(z + 1, 0), nz - 1);
   const size_t pa = (size_t)za * ny * nx, pb = (size_t)zb * ny * nx;
-  E* o = dst + (size_t)packed_index(ix, iy, iz, row, plane) * CORNERS;
+  E* o = dst + (size_t)packed_index(ix, iy, iz, bx, by, bz, row, plane) * CORNERS;
   o[0] = src[pa + (size_t)ya * nx + xa];
   o[1] = src[pa + (size_t)ya * nx + xb];
   o[2] = src[pa + (size_t)yb * nx + xa];
@@ -277,9 +277,7 @@ long long residency_lds(int blocks_per_cu, size_t static_lds) {
 // The residency cap in force for a render of this dtype and layout.
 template <int DT, int LAYOUT>
 static int render_cap() {
-  const int t = tuning().render_blocks_per_cu;
-  if (t >= 0) return t;
-  return DT == DT_F32 && LAYOUT != LAYOUT_DENSE ? 3 : 0;
+  return tuning().render_blocks_per_cu;
 }
 
 template <int DT, int LAYOUT, bool DETAIL>
@@ -375,29 +373,30 @@ hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParam
 }
 
 hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,
-                       void* dst, hipStream_t s) {
+                       const int* brick, void* dst, hipStream_t s) {
   const int ez = layout == LAYOUT_OCT ? nz + 1 : nz;
   const long long entries = (long long)(nx + 1) * (ny + 1) * ez;
   const unsigned blocks = (unsigned)((entries + 255) / 256);
   long long row, plane, stored;
-  packed_strides(nx + 1, ny + 1, ez, &row, &plane, &stored);
+  const int bx = brick[0], by = brick[1], bz = brick[2];
+  packed_strides(nx + 1, ny + 1, ez, bx, by, bz, &row, &plane, &stored);
   if (elem_bytes == 4) {
     if (layout == LAYOUT_OCT)
       hipLaunchKernelGGL((pack_kernel<uint32_t, 8>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, (int)row, (int)plane,
+                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, bx, by, bz, (int)row, (int)plane,
                          static_cast<uint32_t*>(dst));
     else
       hipLaunchKernelGGL((pack_kernel<uint32_t, 4>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, (int)row, (int)plane,
+                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, bx, by, bz, (int)row, (int)plane,
                          static_cast<uint32_t*>(dst));
   } else {
     if (layout == LAYOUT_OCT)
       hipLaunchKernelGGL((pack_kernel<uint16_t, 8>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, (int)row, (int)plane,
+                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, bx, by, bz, (int)row, (int)plane,
                          static_cast<uint16_t*>(dst));
     else
       hipLaunchKernelGGL((pack_kernel<uint16_t, 4>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, (int)row, (int)plane,
+                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, bx, by, bz, (int)row, (int)plane,
                          static_cast<uint16_t*>(dst));
   }
   return hipGetLastError();

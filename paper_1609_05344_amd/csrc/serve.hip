@@ -21,12 +21,15 @@ namespace cloud {
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Index of the request owning global tile t (requests are in tile order).
+// Index of the request owning global tile t (requests are in tile order);
+// RESOLVE selects the resolve tiling instead of the render tiling.
+template <bool RESOLVE = false>
 __device__ __forceinline__ int find_item(const ServeTable* tab, int n_items, int t) {
   int lo = 0, hi = n_items - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (tab->items[mid].tile_begin <= t) lo = mid;
+    const int begin = RESOLVE ? tab->items[mid].taa_tile_begin : tab->items[mid].tile_begin;
+    if (begin <= t) lo = mid;
     else hi = mid - 1;
   }
   return __builtin_amdgcn_readfirstlane(lo);
@@ -76,25 +79,27 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol, ServeT
   }
 }
 
-// Batched temporal resolve: every tile of every request, grid-strided. A
-// request without usable history copies its frame; otherwise the 3x3
-// neighbourhood clamp and blend of the single-frame resolve. The result goes
-// to the stream's history and to the caller's output.
+// Batched temporal resolve: every resolve tile (32 x 8 pixels, rows of whole
+// 128-byte lines) of every request, grid-strided. A request without usable
+// history copies its frame; otherwise the 3x3 neighbourhood clamp and blend
+// of the single-frame resolve, the tile and its one-pixel halo staged in LDS.
+// The result goes to the stream's history and to the caller's output.
 __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* tab) {
-  __shared__ float4 tile[18][18];
-  const int total = tab->total_tiles, n_items = tab->n_items;
+  constexpr int TW = kServeTaaW, TH = kServeTaaH;
+  __shared__ float4 tile[TH + 2][TW + 2];
+  const int total = tab->total_taa_tiles, n_items = tab->n_items;
   const float blend = tab->blend;
+  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    const int i = find_item(tab, n_items, t);
+    const int i = find_item<true>(tab, n_items, t);
     const ServeItem& it = tab->items[i];
     const int W = it.width, H = it.height;
-    const int k = t - it.tile_begin;
-    const int tyi = k / it.tiles_x, txi = k - tyi * it.tiles_x;
-    const int bx = txi * 16, by = tyi * 16;
+    const int k = t - it.taa_tile_begin;
+    const int tyi = k / it.taa_tiles_x, txi = k - tyi * it.taa_tiles_x;
+    const int bx = txi * TW, by = tyi * TH;
     const float4* cur = static_cast<const float4*>(it.cur);
     float4* hist = static_cast<float4*>(it.hist);
     float4* out = static_cast<float4*>(it.out);
-    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
     const int px = bx + lx, py = by + ly;
     const bool inside = px < W && py < H;
     const size_t p = (size_t)py * W + px;
@@ -106,8 +111,8 @@ __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* tab) {
       }
       continue;
     }
-    for (int e = threadIdx.x; e < 18 * 18; e += 256) {
-      const int ey = e / 18, ex = e - ey * 18;
+    for (int e = threadIdx.x; e < (TH + 2) * (TW + 2); e += 256) {
+      const int ey = e / (TW + 2), ex = e - ey * (TW + 2);
       const int gx = min(max(bx + ex - 1, 0), W - 1);
       const int gy = min(max(by + ey - 1, 0), H - 1);
       tile[ey][ex] = cur[(size_t)gy * W + gx];
@@ -195,7 +200,7 @@ class HipExecutor : public serve::Executor {
                                                      256, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 4;
     render_blocks_ = cus * per_cu;
-    taa_blocks_ = cus * 4;
+    taa_blocks_ = cus * 8;
     for (int q = 0; q < queues_; ++q)
       if ((e = hipStreamCreateWithFlags(&stream_[q], hipStreamNonBlocking)) != hipSuccess) return err(e, msg);
     for (int s = 0; s < kSlots; ++s) {
@@ -239,7 +244,7 @@ class HipExecutor : public serve::Executor {
 
   int launch(int slot, const std::vector<serve::Item>& items) override {
     ServeTable* t = host_[slot];
-    int tile = 0;
+    int tile = 0, taa_tile = 0;
     for (size_t i = 0; i < items.size(); ++i) {
       const serve::Item& r = items[i];
       ServeItem& it = t->items[i];
@@ -252,6 +257,9 @@ class HipExecutor : public serve::Executor {
       it.tiles_x = (r.width + 15) / 16;
       it.tiles_y = (r.height + 15) / 16;
       it.tile_begin = tile;
+      it.taa_tiles_x = (r.width + kServeTaaW - 1) / kServeTaaW;
+      it.taa_tile_begin = taa_tile;
+      taa_tile += it.taa_tiles_x * ((r.height + kServeTaaH - 1) / kServeTaaH);
       it.reset = r.reset_history ? 1 : 0;
       it.frame = r.frame;
       const size_t half = stream_bytes(r.width, r.height) / 2;
@@ -262,6 +270,7 @@ class HipExecutor : public serve::Executor {
     }
     std::memset(t->counters, 0, sizeof t->counters);
     t->total_tiles = tile;
+    t->total_taa_tiles = taa_tile;
     t->n_items = (int)items.size();
     t->blend = blend_;
     t->supertile = tuning().supertile;

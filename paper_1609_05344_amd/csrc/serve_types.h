@@ -13,16 +13,19 @@
 namespace cloud {
 
 constexpr int kMaxBatch = 64;   // requests per batch
+constexpr int kServeTaaW = 32, kServeTaaH = 8;   // resolve tile (256 pixels, full-line rows)
 
 struct ServeItem {
   DevCamera cam;
   DevParams prm;
   int width, height;
   int tiles_x, tiles_y;
-  int tile_begin;               // first global tile of this request
+  int tile_begin;               // first global render tile (16 x 16) of this request
   int reset;                    // 1: no usable history, the frame is copied
   uint32_t frame;
-  int pad;
+  int taa_tiles_x;              // resolve tiles (kServeTaaW x kServeTaaH) per row
+  int taa_tile_begin;           // first global resolve tile of this request
+  int pad[3];
   void* cur;                    // [H][W] float4 scratch: this frame before resolve
   void* hist;                   // [H][W] float4 history (stream state)
   void* out;                    // [H][W] float4 caller output
@@ -31,6 +34,7 @@ struct ServeItem {
 struct ServeTable {
   unsigned int counters[8];     // per-XCD render work counters
   int total_tiles;
+  int total_taa_tiles;
   int n_items;
   float blend;
   int supertile;

@@ -86,3 +86,32 @@ def test_argument_errors_before_any_launch(lib):
     assert rc == _lib.CLOUD_E_INVALID and "n_views" in _lib.last_error()
     # a successful-looking call leaves the error text of the last failure only
     assert lib.cloud_jitter_offsets(None, 0, 0, 0, None, None) == _lib.CLOUD_OK
+
+
+def test_packed_bytes_and_brick_shapes(lib):
+    # a host-side size query: no device memory is touched
+    vol = _lib.cloud_volume()
+    vol.nx, vol.ny, vol.nz, vol.dtype = 32, 20, 9, 1       # f16
+    n = ctypes.c_uint64(0)
+
+    def size(layout, brick):
+        vol.brick_log2[:] = list(brick)
+        rc = lib.cloud_volume_packed_bytes(ctypes.byref(vol), layout, ctypes.byref(n))
+        return rc, int(n.value)
+
+    def up(e, b):
+        return -(-e // (1 << b)) << b
+
+    ex, ey = 33, 21
+    for brick in ((1, 1, 1), (2, 0, 1), (3, 0, 0), (0, 0, 3), (1, 0, 2)):
+        for layout, ez, corners in ((1, 9, 4), (2, 10, 8)):
+            rc, got = size(layout, brick)
+            assert rc == _lib.CLOUD_OK
+            want = up(ex, brick[0]) * up(ey, brick[1]) * up(ez, brick[2]) * corners * 2
+            assert got == want, (brick, layout, got, want)
+    assert size(1, (0, 0, 0)) == size(1, (1, 1, 1))      # all zero = the default shape
+    for bad in ((1, 1, 0), (2, 2, 0), (4, 0, -1), (-1, 2, 2)):
+        rc, _ = size(2, bad)
+        assert rc == _lib.CLOUD_E_INVALID and "brick_log2" in _lib.last_error()
+    rc, dense = size(0, (5, 5, 5))                       # dense volumes ignore the shape
+    assert rc == _lib.CLOUD_OK and dense == 32 * 20 * 9 * 2

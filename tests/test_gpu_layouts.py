@@ -49,6 +49,22 @@ def test_packed_equals_dense(cf, dtype, layout):
     assert a[..., 3].max() > 0.5
 
 
+@pytest.mark.parametrize("brick", [(3, 0, 0), (0, 3, 0), (0, 0, 3), (1, 0, 2), (2, 1, 0)])
+@pytest.mark.parametrize("layout", ["quad", "oct"])
+def test_brick_shapes_render_bitwise_equal(cf, layout, brick):
+    w = scenes.workload("H")
+    say(f"{layout} bricks {brick}: 640x360 frames vs dense, bitwise; a 32^3 volume (odd entry counts) too")
+    for sc in (scenes.make_scene(w, dtype="f16"), scenes.make_scene(scenes.workload("C1"))):
+        dense = cf.device_volume(sc)
+        packed = cf.cloud_volume_pack(dense, layout, brick=brick)
+        assert list(packed.struct.brick_log2) == list(brick)
+        cam = w.camera(5) if sc.workload.name == "H" else sc.workload.camera(0)
+        a = to_np(cf.cloud_render(dense, cam, w.params, 5, 640, 360))
+        b = to_np(cf.cloud_render(packed, cam, w.params, 5, 640, 360))
+        assert np.array_equal(a, b)
+        assert a[..., 3].max() > 0.3
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
 @pytest.mark.parametrize("layout", ["quad", "oct"])
 def test_packed_small_volumes_vs_oracle(cf, dtype, layout):
@@ -76,9 +92,10 @@ def test_pack_errors(cf):
     dense = cf.device_volume(scenes.make_scene(w))
     with pytest.raises(cf.CloudError):
         cf.cloud_volume_pack(dense, "dense")
+    # 2x2x2-entry bricks: each entry axis rounded up to an even count
     n = cf.cloud_volume_packed_bytes(dense, "oct")
-    assert n == 33 * 33 * 33 * 8 * 4
-    assert cf.cloud_volume_packed_bytes(dense, "quad") == 33 * 33 * 32 * 4 * 4
+    assert n == 34 * 34 * 34 * 8 * 4
+    assert cf.cloud_volume_packed_bytes(dense, "quad") == 34 * 34 * 32 * 4 * 4
     small = torch.empty((n // 2,), dtype=torch.uint8, device="cuda")
     from paper_1609_05344_amd import _lib
     import ctypes

@@ -30,6 +30,12 @@ constexpr int kLightUnroll = CLOUD_LIGHT_UNROLL;
 #ifndef CLOUD_OCC_SELECT
 #define CLOUD_OCC_SELECT 1
 #endif
+// FP16 volumes: the four x-lerps of a lookup as half-precision dot products
+// accumulated in float32, a + w (b - a) = dot((a, b), (-w, w)) + a with w
+// rounded to half (1), or every lerp in float32 after decoding (0).
+#ifndef CLOUD_HALF_DOT
+#define CLOUD_HALF_DOT 1
+#endif
 #if CLOUD_OCC_SELECT
 #define CLOUD_SKIP_DEAD(live) ((void)0)
 #else
@@ -180,6 +186,12 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
       else c[k] = __uint_as_float(w[k] << 16);
     }
   }
+  // 16-bit texels as (x0, x1) pairs, low half first: rows (y0, z0), (y1, z0),
+  // (y0, z1), (y1, z1).
+  __device__ static __forceinline__ void pairs(const uint32_t (&w)[kWords], uint32_t (&p)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = w[2 * k] | (w[2 * k + 1] << 16);
+  }
 };
 
 // Entry of the footprint with corner k (kx, ky in [-1, n-1]) in packed plane
@@ -228,6 +240,10 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
   __device__ static __forceinline__ void decode(const uint32_t (&w)[kWords], float (&c)[8]) {
     decode_packed<DT>(w, c);
   }
+  __device__ static __forceinline__ void pairs(const uint32_t (&w)[kWords], uint32_t (&p)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = w[k];
+  }
 };
 
 // Oct layout [nz+1][ny+1][nx+1] x 8: entry (z, y, x) holds the whole 2x2x2
@@ -253,6 +269,10 @@ struct BaseSampler<DT, LAYOUT_OCT> {
   __device__ static __forceinline__ void decode(const uint32_t (&w)[kWords], float (&c)[8]) {
     decode_packed<DT>(w, c);
   }
+  __device__ static __forceinline__ void pairs(const uint32_t (&w)[kWords], uint32_t (&p)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = w[k];
+  }
 };
 
 // Trilinear lookup of the base volume at continuous texel coordinates f.
@@ -268,11 +288,25 @@ __device__ __forceinline__ float base_lookup(const DevVolume& v, float fx, float
   CLOUD_SKIP_DEAD(live);
   uint32_t w[S::kWords];
   S::load(v, kx, ky, kz, live, w);
-  float c[8];
-  S::decode(w, c);
-  const float c0 = lerp(lerp(c[0], c[1], wx), lerp(c[2], c[3], wx), wy);
-  const float c1 = lerp(lerp(c[4], c[5], wx), lerp(c[6], c[7], wx), wy);
-  return live ? lerp(c0, c1, wz) : 0.0f;
+  if constexpr (DT == DT_F16 && CLOUD_HALF_DOT) {
+    uint32_t p[4];
+    S::pairs(w, p);
+    const half2_t wt = {(_Float16)(-wx), (_Float16)wx};
+    float c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const half2_t h = __builtin_bit_cast(half2_t, p[k]);
+      c[k] = __builtin_amdgcn_fdot2(h, wt, (float)h.x, false);
+    }
+    const float c0 = lerp(c[0], c[1], wy), c1 = lerp(c[2], c[3], wy);
+    return live ? lerp(c0, c1, wz) : 0.0f;
+  } else {
+    float c[8];
+    S::decode(w, c);
+    const float c0 = lerp(lerp(c[0], c[1], wx), lerp(c[2], c[3], wx), wy);
+    const float c1 = lerp(lerp(c[4], c[5], wx), lerp(c[6], c[7], wx), wy);
+    return live ? lerp(c0, c1, wz) : 0.0f;
+  }
 }
 
 // Index k of a periodic axis of n texels, wrapped into [0, n).

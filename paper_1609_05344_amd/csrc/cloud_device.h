@@ -30,11 +30,17 @@ constexpr int kLightUnroll = CLOUD_LIGHT_UNROLL;
 #ifndef CLOUD_OCC_SELECT
 #define CLOUD_OCC_SELECT 1
 #endif
-// FP16 volumes: the four x-lerps of a lookup as half-precision dot products
+// 16-bit volumes: the four x-lerps of a lookup as 16-bit dot products
 // accumulated in float32, a + w (b - a) = dot((a, b), (-w, w)) + a with w
-// rounded to half (1), or every lerp in float32 after decoding (0).
+// rounded to the storage type (1), or every lerp in float32 after decoding
+// (0). CLOUD_HALF_DOT covers FP16 (on by default: it saves the half-to-float
+// conversions), CLOUD_BF16_DOT BF16 (off: BF16 decodes with a shift, so the
+// dot products save nothing while the 8-bit weight costs accuracy).
 #ifndef CLOUD_HALF_DOT
 #define CLOUD_HALF_DOT 1
+#endif
+#ifndef CLOUD_BF16_DOT
+#define CLOUD_BF16_DOT 0
 #endif
 #if CLOUD_OCC_SELECT
 #define CLOUD_SKIP_DEAD(live) ((void)0)
@@ -80,6 +86,7 @@ __device__ __forceinline__ float jitter_for(int m, uint32_t px, uint32_t py, uin
 // ---------------------------------------------------------------------------
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
 
 template <int DT>
 __device__ __forceinline__ float texel(const void* __restrict__ base, int idx) {
@@ -139,7 +146,7 @@ __device__ __forceinline__ bool occupied(const DevVolume& v, int kx, int ky, int
   const int bx = min(max(kx, 0), v.nx - 1) >> v.occ_lg;
   const int by = min(max(ky, 0), v.ny - 1) >> v.occ_lg;
   const int bz = min(max(kz, 0), v.nz - 1) >> v.occ_lg;
-  const int b = (bz * v.occ_nby + by) * v.occ_nbx + bx;
+  const int b = mul24(mul24(bz, v.occ_nby) + by, v.occ_nbx) + bx;   // < 32768
   return (s_occupancy[b >> 5] >> (b & 31)) & 1u;
 }
 
@@ -226,14 +233,15 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
     const int ia = packed_entry(v, kx, ky, za), ib = packed_entry(v, kx, ky, zb);
     const int ea = live ? ia : 0;
     const int eb = live ? ib : 0;
+    // entries are non-negative: index with 32-bit unsigned offsets
     if constexpr (DT == DT_F32) {
       const uint4* q = static_cast<const uint4*>(v.base);
-      const uint4 A = q[ea], B = q[eb];
+      const uint4 A = q[(uint32_t)ea], B = q[(uint32_t)eb];
       w[0] = A.x; w[1] = A.y; w[2] = A.z; w[3] = A.w;
       w[4] = B.x; w[5] = B.y; w[6] = B.z; w[7] = B.w;
     } else {
       const uint2* q = static_cast<const uint2*>(v.base);
-      const uint2 A = q[ea], B = q[eb];
+      const uint2 A = q[(uint32_t)ea], B = q[(uint32_t)eb];
       w[0] = A.x; w[1] = A.y; w[2] = B.x; w[3] = B.y;
     }
   }
@@ -257,12 +265,12 @@ struct BaseSampler<DT, LAYOUT_OCT> {
     const int ie = packed_entry(v, kx, ky, min(kz, v.nz - 1) + 1);
     const int e = live ? ie : 0;
     if constexpr (DT == DT_F32) {
-      const uint4* q = static_cast<const uint4*>(v.base) + 2 * (size_t)e;
+      const uint4* q = static_cast<const uint4*>(v.base) + 2 * (size_t)(uint32_t)e;
       const uint4 A = q[0], B = q[1];
       w[0] = A.x; w[1] = A.y; w[2] = A.z; w[3] = A.w;
       w[4] = B.x; w[5] = B.y; w[6] = B.z; w[7] = B.w;
     } else {
-      const uint4 Q = static_cast<const uint4*>(v.base)[e];
+      const uint4 Q = static_cast<const uint4*>(v.base)[(uint32_t)e];
       w[0] = Q.x; w[1] = Q.y; w[2] = Q.z; w[3] = Q.w;
     }
   }
@@ -288,15 +296,23 @@ __device__ __forceinline__ float base_lookup(const DevVolume& v, float fx, float
   CLOUD_SKIP_DEAD(live);
   uint32_t w[S::kWords];
   S::load(v, kx, ky, kz, live, w);
-  if constexpr (DT == DT_F16 && CLOUD_HALF_DOT) {
+  if constexpr ((DT == DT_F16 && CLOUD_HALF_DOT) || (DT == DT_BF16 && CLOUD_BF16_DOT)) {
     uint32_t p[4];
     S::pairs(w, p);
-    const half2_t wt = {(_Float16)(-wx), (_Float16)wx};
     float c[4];
+    if constexpr (DT == DT_F16) {
+      const half2_t wt = {(_Float16)(-wx), (_Float16)wx};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const half2_t h = __builtin_bit_cast(half2_t, p[k]);
-      c[k] = __builtin_amdgcn_fdot2(h, wt, (float)h.x, false);
+      for (int k = 0; k < 4; ++k) {
+        const half2_t h = __builtin_bit_cast(half2_t, p[k]);
+        c[k] = __builtin_amdgcn_fdot2(h, wt, (float)h.x, false);
+      }
+    } else {
+      const bf162_t wt = {(__bf16)(-wx), (__bf16)wx};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        c[k] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf162_t, p[k]), wt,
+                                               __uint_as_float(p[k] << 16), false);
     }
     const float c0 = lerp(c[0], c[1], wy), c1 = lerp(c[2], c[3], wy);
     return live ? lerp(c0, c1, wz) : 0.0f;

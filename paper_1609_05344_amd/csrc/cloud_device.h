@@ -474,10 +474,9 @@ template <int DT, int LAYOUT, bool DETAIL>
 __device__ __forceinline__ float light_transmittance(const DevVolume& v, const DevParams& P,
                                                      float px, float py, float pz) {
   const LightPath lp = light_path<DETAIL>(v, P, px, py, pz);
-  float acc = 0.0f;
+  float acc = 0.0f, h = 0.5f;   // h = k + 1/2, exact in float32
 #pragma unroll kLightUnroll
-  for (int k = 0; k < P.light_steps; ++k) {
-    const float h = (float)k + 0.5f;
+  for (int k = 0; k < P.light_steps; ++k, h += 1.0f) {
     acc += density_tex<DT, LAYOUT, DETAIL>(v, fmaf(h, lp.dfx, lp.fx0), fmaf(h, lp.dfy, lp.fy0),
                                            fmaf(h, lp.dfz, lp.fz0), fmaf(h, lp.dgx, lp.gx0),
                                            fmaf(h, lp.dgy, lp.gy0), fmaf(h, lp.dgz, lp.gz0));
@@ -623,6 +622,19 @@ __device__ __forceinline__ void camera_dir(const DevCamera& c, int px, int py, i
   dx = ux * inv;
   dy = uy * inv;
   dz = uz * inv;
+}
+
+// Pixel of a lane in a 16x16 render tile (tx, ty): the four wavefronts of
+// the workgroup each cover a CLOUD_WAVE_W x (64 / CLOUD_WAVE_W) patch (8x8 by
+// default), so the 64 rays of a wavefront are a compact bundle.
+#ifndef CLOUD_WAVE_W
+#define CLOUD_WAVE_W 8
+#endif
+__device__ __forceinline__ void tile_pixel(int tx, int ty, int wave, int lane, int& px, int& py) {
+  constexpr int WW = CLOUD_WAVE_W, WH = 64 / WW, PER_ROW = 16 / WW;
+  static_assert(WW == 4 || WW == 8 || WW == 16, "wave patch width");
+  px = tx * 16 + (wave % PER_ROW) * WW + lane % WW;
+  py = ty * 16 + (wave / PER_ROW) * WH + lane / WW;
 }
 
 // Block index -> tile index so that each XCD (workgroups are dealt to the 8

@@ -52,8 +52,8 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
   int tx, ty;
   supertile(tile - view * tiles_per_view, tiles_x, tiles_y, S, tx, ty);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int px = tx * 16 + (wave & 1) * 8 + (lane & 7);
-  const int py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+  int px, py;
+  tile_pixel(tx, ty, wave, lane, px, py);
   const bool inside = px < W && py < H;
   stage_occupancy(vol);
   if (!COUNT && !inside) return;

@@ -64,8 +64,8 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol, ServeT
     int tx, ty;
     supertile(t - it.tile_begin, it.tiles_x, it.tiles_y, S, tx, ty);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int px = tx * 16 + (wave & 1) * 8 + (lane & 7);
-    const int py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    int px, py;
+    tile_pixel(tx, ty, wave, lane, px, py);
     if (px < it.width && py < it.height) {
       float dx, dy, dz;
       camera_dir(it.cam, px, py, it.width, it.height, dx, dy, dz);

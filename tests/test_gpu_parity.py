@@ -194,6 +194,47 @@ def test_ragged_sizes(cf, torch, W, H):
     assert max_err(got, want) < FP32_TOL
 
 
+@pytest.mark.parametrize("W,H", [(65536, 2), (3, 65536)])
+def test_maximum_image_extents_sampled(cf, torch, W, H):
+    # the largest width and height the library accepts, on thin images
+    say(f"maximum extent {W}x{H}: sampled parity")
+    w = scenes.workload("C2")
+    sc = scenes.make_scene(w)
+    cam = scenes.Camera(pos=(0.0, 0.05, 1.2), target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0),
+                        vfov_deg=50.0)
+    got = to_np(cf.cloud_render(cf.device_volume(sc, layout="oct", occupancy=True), cam,
+                                w.params, 2, W, H))
+    pix = scenes.random_pixels(W, H, 1500, seed=W + H)
+    ends = np.array([[0, 0], [W - 1, 0], [0, H - 1], [W - 1, H - 1]])
+    # with so extreme an aspect only the rays next to the centre line meet the
+    # volume: take a band around it as well
+    band = np.array([[x, y] for x in range(max(W // 2 - 24, 0), min(W // 2 + 24, W))
+                     for y in range(max(H // 2 - 24, 0), min(H // 2 + 24, H))])
+    pix = np.concatenate([pix, ends, band])
+    want = O.render(oracle_volume(sc), cam, w.params, W, H, frame=2, pixels=pix)
+    assert max_err(got[pix[:, 1], pix[:, 0]], want) < FP32_TOL
+    assert want[:, 3].max() > 0.05
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (257, 3, 2), (2, 300, 5)])
+@pytest.mark.parametrize("layout", ["dense", "quad", "oct"])
+def test_degenerate_volume_shapes(cf, torch, dims, layout):
+    # the smallest volume and long thin ones, every layout, against the oracle
+    say(f"volume {dims} {layout}: full frame vs oracle")
+    w = scenes.workload("C1", jitter=1)
+    rng = np.random.default_rng(sum(dims))
+    nx, ny, nz = dims
+    base = np.clip(rng.uniform(-0.3, 1.0, size=(nz, ny, nx)), 0, 1)
+    st = scenes.quantise(base, "f32")
+    sc = scenes.Scene(w, st, scenes.decode(st, "f32"))
+    vol = cf.device_volume(sc, layout=layout, occupancy=layout != "dense")
+    cam = scenes.orbit_camera(1.6, 205.0, 30.0)
+    got = to_np(cf.cloud_render(vol, cam, w.params, 1, 48, 40))
+    want = O.render(oracle_volume(sc), cam, w.params, 48, 40, frame=1)
+    assert max_err(got, want) < FP32_TOL
+    assert want[..., 3].max() > 0.05
+
+
 @pytest.mark.parametrize("name,frame", [("C2", 0), ("C2", 9), ("C2ref", 0), ("H", 3)])
 def test_full_size_sampled(cf, torch, name, frame):
     w = scenes.workload(name)

@@ -40,7 +40,10 @@
 extern "C" {
 #endif
 
-#define CLOUD_ABI_VERSION 1
+/* Raised whenever a struct layout or a signature changes (2: brick_log2 in
+ * cloud_volume, queues in cloud_serve_config, depth/trace/ceiling/composite
+ * entry points). */
+#define CLOUD_ABI_VERSION 2
 
 enum {
   CLOUD_OK = 0,

@@ -59,8 +59,12 @@ class cloud_params(ctypes.Structure):
 _lib = None
 
 
+ABI_VERSION = 2   # the struct layouts and signatures this binding marshals
+
+
 def load():
-    """Load libcloud.so once; raises if it is missing (no fallback exists)."""
+    """Load libcloud.so once; raises if it is missing or was built for
+    another ABI version (no fallback exists)."""
     global _lib
     if _lib is not None:
         return _lib
@@ -70,6 +74,9 @@ def load():
     lib.cloud_last_error.restype = c_char_p
     lib.cloud_last_error.argtypes = []
     lib.cloud_abi_version.restype = c_int
+    if lib.cloud_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {lib.cloud_abi_version()}, this binding "
+                           f"needs {ABI_VERSION}; rebuild with `python -m paper_1609_05344_amd.build`")
     lib.cloud_render.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), POINTER(cloud_params),
                                  c_uint32, c_int32, c_int32, c_void_p, c_void_p]
     lib.cloud_render_views.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,

@@ -221,9 +221,10 @@ __device__ __forceinline__ void decode_packed(const uint32_t (&w)[N], float (&c)
   }
 }
 
-// Quad layout [nz][ny+1][nx+1] x 4: entry (z, y, x) holds the texels at
-// (x, y), (x+1, y), (x, y+1), (x+1, y+1) of plane z (edge-clamped), so a
-// lookup is two aligned fetches, one per z plane.
+// Quad layout, nz x (ny+1) x (nx+1) entries of 4 texels in bricks (see
+// packed_index): entry (z, y, x) holds the texels at (x, y), (x+1, y),
+// (x, y+1), (x+1, y+1) of plane z (edge-clamped), so a lookup is two aligned
+// fetches, one per z plane.
 template <int DT>
 struct BaseSampler<DT, LAYOUT_QUAD> {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
@@ -254,9 +255,10 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
   }
 };
 
-// Oct layout [nz+1][ny+1][nx+1] x 8: entry (z, y, x) holds the whole 2x2x2
-// footprint (the quad of plane z, then the quad of plane z+1, edge-clamped),
-// so a lookup is one aligned fetch (two for float32).
+// Oct layout, (nz+1) x (ny+1) x (nx+1) entries of 8 texels in bricks: entry
+// (z, y, x) holds the whole 2x2x2 footprint (the quad of plane z, then the
+// quad of plane z+1, edge-clamped), so a lookup is one aligned fetch (two for
+// float32).
 template <int DT>
 struct BaseSampler<DT, LAYOUT_OCT> {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;

@@ -234,10 +234,13 @@ def gather_ceiling(cf, torch, np, w, vol, p, frames, render_ms: float, bytes_per
 # ---------------------------------------------------------------------------
 
 def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams: int,
-                       seconds: float, warm_s: float = 0.5, queues: int = 1) -> dict:
+                       seconds: float, warm_s: float = 0.5, queues: int = 1,
+                       graphs: bool = True) -> dict:
     """n_streams streams of the workload, each submitting its next frame as
     soon as the previous one completes; frames/s and frame latency
-    (submit -> done) over the measured window."""
+    (submit -> done) over the measured window. A multi-view workload gives
+    stream s the camera of view s (mod the view count). graphs=False makes the
+    server launch its kernels one by one instead of replaying captured graphs."""
     import numpy as np
     sc = scenes.make_scene(w, dtype=dtype)
     vol = cf.device_volume(sc, layout=layout, occupancy=True)
@@ -246,14 +249,17 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
     frame = [0] * n_streams
     lat, done_t = [], []
 
-    def orbit(s, f):
+    def camera(s, f):
         # the same stretch of the orbit (frames 10..69) that the plain leg times
-        return 10 + (s + f) % 60
+        if w.views > 1:
+            return w.camera(10 + f % 60, view=s % w.views)
+        return w.camera(10 + (s + f) % 60)
 
-    with cf.Server(vol, budget_bytes=n_streams * W * H * 40, max_batch=64, queues=queues) as srv:
+    with cf.Server(vol, budget_bytes=n_streams * W * H * 40, max_batch=64, queues=queues,
+                   use_graphs=graphs) as srv:
         t_start = time.monotonic()
         for s in range(n_streams):
-            srv.submit(s, w.camera(orbit(s, 0)), w.params, W, H, 0, outs[s])
+            srv.submit(s, camera(s, 0), w.params, W, H, 0, outs[s])
         t_end = t_start + warm_s + seconds
         while time.monotonic() < t_end:
             got = srv.poll(256)
@@ -267,7 +273,7 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
                     lat.append((c["t_done_ns"] - c["t_submit_ns"]) * 1e-6)
                     done_t.append(c["t_done_ns"] * 1e-9)
                 frame[s] += 1
-                srv.submit(s, w.camera(orbit(s, frame[s])), w.params, W, H, frame[s], outs[s])
+                srv.submit(s, camera(s, frame[s]), w.params, W, H, frame[s], outs[s])
         st = srv.stats()
     done_t.sort()
     span = done_t[-1] - done_t[0] if len(done_t) > 1 else float("nan")
@@ -276,7 +282,7 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
             "frames_per_s": round(fps, 1), "ms_per_frame": round(1e3 / fps, 4) if fps else None,
             "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
             "latency_p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "frames": len(lat), "batches": st["batches"], "queues": queues}
+            "frames": len(lat), "batches": st["batches"], "queues": queues, "graphs": graphs}
 
 
 def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: float = 1.0,
@@ -449,7 +455,9 @@ def main():
     ap.add_argument("--workload", default="H")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--layout", default="quad", choices=["dense", "quad", "oct"])
-    ap.add_argument("--served-streams", type=int, default=64)
+    ap.add_argument("--served-streams", type=int, default=0,
+                    help="closed-loop streams of the served leg (0: 64, or the view count of a "
+                         "multi-view workload)")
     ap.add_argument("--served-seconds", type=float, default=2.0)
     ap.add_argument("--served-dtype", default="f16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--served-layout", default="oct", choices=["dense", "quad", "oct"])
@@ -465,6 +473,8 @@ def main():
     ap.add_argument("--no-ceiling", action="store_true",
                     help="skip the gather-ceiling measurement")
     ap.add_argument("--serve-queues", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--serve-graphs", type=int, default=1, choices=[0, 1],
+                    help="served leg: 1 replays captured graphs, 0 launches kernels one by one")
     ap.add_argument("--no-occupancy", action="store_true",
                     help="render without the exact empty-space-skipping bitmap")
     ap.add_argument("--serve-poisson", default="",
@@ -657,11 +667,13 @@ def main():
     if not args.no_served:
         del cur, hist, vol
         torch.cuda.empty_cache()
+        n_streams = args.served_streams or (64 if w.views == 1 else w.views)
         served = served_closed_loop(cf, scenes, torch, w, args.served_dtype, args.served_layout,
-                                    args.served_streams, args.served_seconds,
-                                    queues=args.serve_queues)
-        served["plain_frames_per_s"] = round(1e3 / ms_per_step, 1)
-        served["speedup_vs_plain"] = round(served["frames_per_s"] * ms_per_step / 1e3, 3)
+                                    n_streams, args.served_seconds, queues=args.serve_queues,
+                                    graphs=args.serve_graphs == 1)
+        # a plain step renders and resolves every view once
+        served["plain_frames_per_s"] = round(V * 1e3 / ms_per_step, 1)
+        served["speedup_vs_plain"] = round(served["frames_per_s"] * ms_per_step / (1e3 * V), 3)
         line["served"] = served
     print(json.dumps(line), flush=True)
 

@@ -41,9 +41,13 @@ __device__ __forceinline__ int find_item(const ServeTable* tab, int n_items, int
 // so blockIdx % 8 names the XCD a workgroup most likely runs on); a
 // workgroup drains its own range first, then helps the others, so neighbouring
 // tiles tend to share an L2. Every workgroup leaves once all ranges are empty.
+// The table is read-only here apart from its work counters, which come in as
+// their own pointer: with the table const and unaliased, the request fields
+// are scalar loads held in scalar registers rather than per-lane copies.
 template <int DT, int LAYOUT, bool DETAIL>
-__global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol, ServeTable* tab) {
-  unsigned int* counters = tab->counters;
+__global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol,
+                                                           unsigned int* __restrict__ counters,
+                                                           const ServeTable* __restrict__ tab) {
   stage_occupancy(vol);
   __shared__ int s_tile;
   const int total = tab->total_tiles, n_items = tab->n_items, S = tab->supertile;
@@ -155,7 +159,7 @@ struct Payload {
   DevParams prm;
 };
 
-typedef void (*RenderFn)(DevVolume, ServeTable*);
+typedef void (*RenderFn)(DevVolume, unsigned int*, const ServeTable*);
 
 template <int DT, int LAYOUT>
 RenderFn pick_l(bool detail) {
@@ -303,7 +307,8 @@ class HipExecutor : public serve::Executor {
     hipError_t e = hipMemcpyAsync(dev_[slot], host_[slot], sizeof(ServeTable),
                                   hipMemcpyHostToDevice, q);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn_, dim3(render_blocks_), dim3(256), 0, q, vol_, dev_[slot]);
+    hipLaunchKernelGGL(fn_, dim3(render_blocks_), dim3(256), 0, q, vol_, dev_[slot]->counters,
+                       static_cast<const ServeTable*>(dev_[slot]));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(serve_taa_kernel, dim3(taa_blocks_), dim3(256), 0, q, dev_[slot]);
     return hipGetLastError();

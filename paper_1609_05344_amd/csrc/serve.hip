@@ -21,6 +21,12 @@ namespace cloud {
 // Kernels
 // ---------------------------------------------------------------------------
 
+// Image pointers come out of the request table as generic pointers; they
+// always address device global memory, so they are used as such (global
+// rather than flat memory instructions).
+typedef __attribute__((address_space(1))) float4 global_float4;
+__device__ __forceinline__ global_float4* as_global(void* p) { return (global_float4*)p; }
+
 // Index of the request owning global tile t (requests are in tile order);
 // RESOLVE selects the resolve tiling instead of the render tiling.
 template <bool RESOLVE = false>
@@ -78,7 +84,7 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol,
       const RayResult r = march<DT, LAYOUT, DETAIL, false>(vol, it.prm, it.cam.pos[0],
                                                            it.cam.pos[1], it.cam.pos[2], dx, dy,
                                                            dz, j);
-      static_cast<float4*>(it.cur)[(size_t)py * it.width + px] = make_float4(r.r, r.g, r.b, r.a);
+      as_global(it.cur)[(size_t)py * it.width + px] = make_float4(r.r, r.g, r.b, r.a);
     }
   }
 }
@@ -88,7 +94,7 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol,
 // history copies its frame; otherwise the 3x3 neighbourhood clamp and blend
 // of the single-frame resolve, the tile and its one-pixel halo staged in LDS.
 // The result goes to the stream's history and to the caller's output.
-__global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* tab) {
+__global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* __restrict__ tab) {
   constexpr int TW = kServeTaaW, TH = kServeTaaH;
   __shared__ float4 tile[TH + 2][TW + 2];
   const int total = tab->total_taa_tiles, n_items = tab->n_items;
@@ -101,9 +107,9 @@ __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* tab) {
     const int k = t - it.taa_tile_begin;
     const int tyi = k / it.taa_tiles_x, txi = k - tyi * it.taa_tiles_x;
     const int bx = txi * TW, by = tyi * TH;
-    const float4* cur = static_cast<const float4*>(it.cur);
-    float4* hist = static_cast<float4*>(it.hist);
-    float4* out = static_cast<float4*>(it.out);
+    const global_float4* cur = as_global(it.cur);
+    global_float4* hist = as_global(it.hist);
+    global_float4* out = as_global(it.out);
     const int px = bx + lx, py = by + ly;
     const bool inside = px < W && py < H;
     const size_t p = (size_t)py * W + px;

@@ -24,7 +24,13 @@ namespace cloud {
 // Image pointers come out of the request table as generic pointers; they
 // always address device global memory, so they are used as such (global
 // rather than flat memory instructions).
+// (The host pass of the compiler only type-checks kernel bodies; it keeps the
+// generic type.)
+#if defined(__HIP_DEVICE_COMPILE__)
 typedef __attribute__((address_space(1))) float4 global_float4;
+#else
+typedef float4 global_float4;
+#endif
 __device__ __forceinline__ global_float4* as_global(void* p) { return (global_float4*)p; }
 
 // Index of the request owning global tile t (requests are in tile order);

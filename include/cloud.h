@@ -334,7 +334,7 @@ int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t ds
                            cloud_volume* with_occupancy, void* hip_stream);
 
 /* Launch-shape knob, process-wide, for tuning and benchmarking; results do
- * not depend on it. Keys: "supertile" (0..64, default 4) -- the render walks
+ * not depend on it. Keys: "supertile" (0..64, default 8) -- the render walks
  * its 16x16-pixel tiles in S x S super-tiles so that the tiles an XCD works on
  * together cover a compact patch of the image (0 = row-major); "taa_tile"
  * (16, 32 or 64, default 32) -- the resolve's tile width in pixels (each

@@ -212,7 +212,7 @@ int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
     d.occ = v->occupancy;
     d.occ_lg = v->occupancy_log2;
     d.occ_nbx = nbx;
-    d.occ_nby = nby;
+    d.occ_plane = nbx * nby;
     d.occ_words = words;
   }
   *out = d;

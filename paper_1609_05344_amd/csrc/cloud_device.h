@@ -114,13 +114,17 @@ __device__ __forceinline__ void unpack2(uint32_t u, float& lo, float& hi) {
 
 __device__ __forceinline__ float lerp(float a, float b, float w) { return fmaf(w, b - a, a); }
 
-// Continuous texel coordinate bounded to [-1, n]: leaves every clamped lookup
-// unchanged and keeps every index inside the volume for any input (NaN too).
+// Continuous texel coordinate bounded to [0, n - 1], split into the corner k
+// and the weight w. Under clamp-to-edge a lookup is constant beyond the outer
+// texel centres, and at the bound w = 0 selects the edge texel exactly, so the
+// bound changes no lookup; it keeps k inside [0, n - 1] for any input (NaN
+// too), which the index arithmetic below relies on.
+// The clamp is one median-of-three (a NaN input gives 0); f >= 0 then, so
+// the fraction is f - floor(f) exactly and truncation is the floor.
 __device__ __forceinline__ void split_coord(float f, int n, float& w, int& k) {
-  f = fminf(fmaxf(f, -1.0f), (float)n);
-  const float fl = floorf(f);
-  w = f - fl;
-  k = (int)fl;   // in [-1, n]
+  f = __builtin_amdgcn_fmed3f(f, 0.0f, (float)(n - 1));
+  w = __builtin_amdgcn_fractf(f);
+  k = (int)f;   // in [0, n - 1]
 }
 
 // ---------------------------------------------------------------------------
@@ -138,15 +142,14 @@ __device__ __forceinline__ void stage_occupancy(const DevVolume& v) {
   __syncthreads();
 }
 
-// False when every texel a footprint with corner k can touch is zero, so the
-// trilinear lookup is exactly 0 (k in [-1, n] per axis; the clamp maps it to
-// the brick holding the texels the lookup reads).
+// False when every texel a footprint with corner k (in [0, n - 1] per axis)
+// can touch is zero, so the trilinear lookup is exactly 0.
 __device__ __forceinline__ bool occupied(const DevVolume& v, int kx, int ky, int kz) {
   if (!v.occ) return true;
-  const int bx = min(max(kx, 0), v.nx - 1) >> v.occ_lg;
-  const int by = min(max(ky, 0), v.ny - 1) >> v.occ_lg;
-  const int bz = min(max(kz, 0), v.nz - 1) >> v.occ_lg;
-  const int b = mul24(mul24(bz, v.occ_nby) + by, v.occ_nbx) + bx;   // < 32768
+  const int bx = kx >> v.occ_lg;
+  const int by = ky >> v.occ_lg;
+  const int bz = kz >> v.occ_lg;
+  const int b = mul24(bz, v.occ_plane) + mul24(by, v.occ_nbx) + bx;   // < 32768
   return (s_occupancy[b >> 5] >> (b & 31)) & 1u;
 }
 
@@ -168,9 +171,9 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
   static constexpr int kWords = 8;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
-    const int xa = min(max(kx, 0), v.nx - 1), xb = min(max(kx + 1, 0), v.nx - 1);
-    const int ya = min(max(ky, 0), v.ny - 1), yb = min(max(ky + 1, 0), v.ny - 1);
-    const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
+    const int xa = kx, xb = min(kx + 1, v.nx - 1);
+    const int ya = ky, yb = min(ky + 1, v.ny - 1);
+    const int za = kz, zb = min(kz + 1, v.nz - 1);
     // indices stay below 2^31 and plane < 2^24 (checked on the host), so the
     // 24-bit multiplies are exact
     const int ra = __umul24(ya, v.row), rb = __umul24(yb, v.row);
@@ -201,11 +204,10 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
   }
 };
 
-// Entry of the footprint with corner k (kx, ky in [-1, n-1]) in packed plane
-// z of a packed volume.
+// Entry of the footprint with corner k (kx, ky in [0, n - 1]) in packed
+// plane z of a packed volume.
 __device__ __forceinline__ int packed_entry(const DevVolume& v, int kx, int ky, int z) {
-  return packed_index(min(kx, v.nx - 1) + 1, min(ky, v.ny - 1) + 1, z, v.bx, v.by, v.bz, v.row,
-                      v.plane);
+  return packed_index(kx + 1, ky + 1, z, v.bx, v.by, v.bz, v.row, v.plane);
 }
 
 // Four float32 texels, or eight 16-bit texels packed two to a word (low half
@@ -230,7 +232,7 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
-    const int za = min(max(kz, 0), v.nz - 1), zb = min(max(kz + 1, 0), v.nz - 1);
+    const int za = kz, zb = min(kz + 1, v.nz - 1);
     const int ia = packed_entry(v, kx, ky, za), ib = packed_entry(v, kx, ky, zb);
     const int ea = live ? ia : 0;
     const int eb = live ? ib : 0;
@@ -264,7 +266,7 @@ struct BaseSampler<DT, LAYOUT_OCT> {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
-    const int ie = packed_entry(v, kx, ky, min(kz, v.nz - 1) + 1);
+    const int ie = packed_entry(v, kx, ky, kz + 1);
     const int e = live ? ie : 0;
     if constexpr (DT == DT_F32) {
       const uint4* q = static_cast<const uint4*>(v.base) + 2 * (size_t)(uint32_t)e;

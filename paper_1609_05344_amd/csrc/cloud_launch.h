@@ -9,7 +9,7 @@ namespace cloud {
 
 // Launch-shape knobs (process-wide; set through cloud_tune).
 struct Tuning {
-  int supertile = 4;   // render tile walk: S x S super-tiles (0 = row-major)
+  int supertile = 8;   // render tile walk: S x S super-tiles (0 = row-major)
   int taa_tile = 32;   // resolve tile width in pixels (16, 32 or 64; 256 pixels a tile)
   // cap on resident render workgroups per CU (0: none, the default; with the
   // bricked packed layouts every measured cap was slower)

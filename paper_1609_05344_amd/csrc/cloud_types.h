@@ -70,9 +70,10 @@ struct DevVolume {
   float dsx, dsy, dsz, dox, doy, doz;
   float detail_weight;
   float bmin[3], bmax[3];
-  // occupancy bitmap (nullptr = none): bricks of 2^occ_lg texels per axis
+  // occupancy bitmap (nullptr = none): bricks of 2^occ_lg texels per axis,
+  // occ_nbx per brick row and occ_plane per brick plane
   const uint32_t* occ;
-  int occ_lg, occ_nbx, occ_nby, occ_words;
+  int occ_lg, occ_nbx, occ_plane, occ_words;
 };
 
 constexpr int kOccupancyWords = 1024;   // LDS budget of the bitmap (32768 bricks)

@@ -334,14 +334,19 @@ int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t ds
                            cloud_volume* with_occupancy, void* hip_stream);
 
 /* Launch-shape knob, process-wide, for tuning and benchmarking; results do
- * not depend on it. Keys: "supertile" (0..64, default 8) -- the render walks
- * its 16x16-pixel tiles in S x S super-tiles so that the tiles an XCD works on
- * together cover a compact patch of the image (0 = row-major); "taa_tile"
- * (16, 32 or 64, default 32) -- the resolve's tile width in pixels (each
- * tile holds 256 pixels); "render_blocks_per_cu" (0..64, default 0 = no cap)
- * -- at most this many render workgroups resident per CU, enforced by
- * reserving LDS at launch (CLOUD_E_INVALID when the device's LDS cannot
- * express it). */
+ * not depend on it. Keys:
+ *  "supertile" (-1..64, default -1 = 4) -- the render walks its 16x16-pixel
+ *      tiles in S x S super-tiles (0 = row-major).
+ *  "xcd_run" (-1..65536, default -1 = S * S) -- the walk is dealt to the 8
+ *      XCDs in rounds of runs of this many tiles (XCD x takes run
+ *      (x + 3j) mod 8 of round j), so that every XCD's share is spread over
+ *      the image (equal work) yet made of compact runs (shared L2); 0 gives
+ *      each XCD one contiguous eighth of the walk.
+ *  "taa_tile" (16, 32 or 64, default 32) -- the resolve's tile width in
+ *      pixels (each tile holds 256 pixels).
+ *  "render_blocks_per_cu" (0..64, default 0 = no cap) -- at most this many
+ *      render workgroups resident per CU, enforced by reserving LDS at
+ *      launch (CLOUD_E_INVALID when the device's LDS cannot express it). */
 int cloud_tune(const char* key, int32_t value);
 
 /* Checks that [ptr, ptr + bytes) lies inside one HIP device allocation: the

@@ -715,8 +715,13 @@ int cloud_tune(const char* key, int32_t value) {
   if (!key) return fail(CLOUD_E_INVALID, "key is NULL");
   const std::string k(key);
   if (k == "supertile") {
-    if (value < 0 || value > 64) return fail(CLOUD_E_INVALID, "supertile must be in [0, 64]");
+    if (value < -1 || value > 64) return fail(CLOUD_E_INVALID, "supertile must be in [-1, 64]");
     tuning().supertile = value;
+    return CLOUD_OK;
+  }
+  if (k == "xcd_run") {
+    if (value < -1 || value > 65536) return fail(CLOUD_E_INVALID, "xcd_run must be in [-1, 65536]");
+    tuning().xcd_run = value;
     return CLOUD_OK;
   }
   if (k == "taa_tile") {

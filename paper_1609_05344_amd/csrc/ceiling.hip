@@ -42,11 +42,11 @@ template <int DT, int LAYOUT, bool RANDOM>
 __global__ __launch_bounds__(256) void gather_ceiling_kernel(DevVolume vol, DevParams prm,
                                                              DevCameras cams, uint32_t frame,
                                                              int W, int H, int tiles_x,
-                                                             int tiles_y, int S,
+                                                             int tiles_y, int S, int L,
                                                              const uint2* __restrict__ trace,
                                                              float4* __restrict__ out) {
   const int tiles_per_view = tiles_x * tiles_y;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = xcd_walk(blockIdx.x, gridDim.x, L);
   const int view = tile / tiles_per_view;
   int tx, ty;
   supertile(tile - view * tiles_per_view, tiles_x, tiles_y, S, tx, ty);
@@ -125,12 +125,13 @@ static hipError_t ceiling_run(const DevVolume& v, const DevParams& p, const DevC
   if (target <= 0) return hipErrorInvalidValue;
   long long pad = residency_lds(target, attr.sharedSizeBytes);
   if (pad < 0) pad = 0;
+  const TileWalk tw = tile_walk();
   if (random)
     hipLaunchKernelGGL((gather_ceiling_kernel<DT, LAYOUT, true>), grid, dim3(256), (size_t)pad, s,
-                       v, p, c, frame, W, H, tiles_x, tiles_y, tuning().supertile, tr, o);
+                       v, p, c, frame, W, H, tiles_x, tiles_y, tw.S, tw.L, tr, o);
   else
     hipLaunchKernelGGL((gather_ceiling_kernel<DT, LAYOUT, false>), grid, dim3(256), (size_t)pad, s,
-                       v, p, c, frame, W, H, tiles_x, tiles_y, tuning().supertile, tr, o);
+                       v, p, c, frame, W, H, tiles_x, tiles_y, tw.S, tw.L, tr, o);
   return hipGetLastError();
 }
 

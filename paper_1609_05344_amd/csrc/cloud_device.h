@@ -641,13 +641,31 @@ __device__ __forceinline__ void tile_pixel(int tx, int ty, int wave, int lane, i
   py = ty * 16 + (wave / PER_ROW) * WH + lane / WW;
 }
 
-// Block index -> tile index so that each XCD (workgroups are dealt to the 8
-// XCDs round-robin) receives one contiguous run of tiles, keeping neighbouring
-// tiles -- which read the same part of the volume -- in the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int x = b & 7, k = b >> 3;
-  return x * q + min(x, r) + k;
+// Block index b of nb -> position in the tile walk. Workgroups are dealt to
+// the 8 XCDs round-robin (b % 8 names the XCD, and each XCD has its own L2).
+// The walk is cut into rounds of 8 runs of L consecutive tiles; in round j,
+// XCD x takes run (x + 3j) mod 8. With L = S * S a run is one super-tile, so
+// the tiles an XCD works on together still share its L2, while its runs are
+// spread over the whole image: the XCDs get near-equal shares of the costly
+// tiles (with one contiguous run each, the XCD holding the densest band of
+// cloud would finish last). The tail that fills no round, or the whole walk
+// when L == 0, is cut into 8 contiguous runs. The map is a bijection on
+// [0, nb).
+__device__ __forceinline__ int xcd_walk(int b, int nb, int L) {
+  const int x = b & 7;
+  int k = b >> 3, base = 0, n = nb;
+  if (L > 0) {
+    const int J = nb / (8 * L);   // full rounds
+    if (k < J * L) {
+      const int j = k / L;
+      return (j * 8 + ((x + 3 * j) & 7)) * L + (k - j * L);
+    }
+    base = 8 * L * J;
+    n = nb - base;
+    k -= J * L;
+  }
+  const int q = n >> 3, r = n & 7;
+  return base + x * q + min(x, r) + k;
 }
 
 // Ordered tile index k of one view -> tile (tx, ty). Tiles are walked in

@@ -9,13 +9,24 @@ namespace cloud {
 
 // Launch-shape knobs (process-wide; set through cloud_tune).
 struct Tuning {
-  int supertile = 8;   // render tile walk: S x S super-tiles (0 = row-major)
+  // render tile walk: S x S super-tiles (0 = row-major; -1 = 4)
+  int supertile = -1;
+  // tiles per XCD run: the walk is dealt to the XCDs in rounds of runs this
+  // long (0: one contiguous eighth per XCD; -1 = S * S, one super-tile)
+  int xcd_run = -1;
   int taa_tile = 32;   // resolve tile width in pixels (16, 32 or 64; 256 pixels a tile)
   // cap on resident render workgroups per CU (0: none, the default; with the
   // bricked packed layouts every measured cap was slower)
   int render_blocks_per_cu = 0;
 };
 Tuning& tuning();
+
+// Render tile walk under the current
+// tuning: super-tile side S and XCD run length L (0 = contiguous runs).
+struct TileWalk {
+  int S, L;
+};
+TileWalk tile_walk();
 
 // Dynamic LDS bytes that cap a 256-thread kernel using static_lds bytes of
 // LDS at blocks_per_cu resident workgroups per CU on the current device (0

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol,
   for (int probe = 0; probe < 8;) {
     const int q = (home + probe) & 7;
     const int b = (int)(((long long)total * q) >> 3), e = (int)(((long long)total * (q + 1)) >> 3);
-    if (threadIdx.x == 0) s_tile = b + (int)atomicAdd(&counters[q], 1u);
+    if (threadIdx.x == 0) s_tile = b + (int)atomicAdd(&counters[q * kCounterStride], 1u);
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(s_tile);
     __syncthreads();
@@ -289,7 +289,7 @@ class HipExecutor : public serve::Executor {
     t->total_taa_tiles = taa_tile;
     t->n_items = (int)items.size();
     t->blend = blend_;
-    t->supertile = tuning().supertile;
+    t->supertile = tile_walk().S;
     hipError_t e;
     if (graphs_) {
       e = hipGraphLaunch(exec_[slot], queue(slot));

@@ -115,3 +115,22 @@ def test_packed_bytes_and_brick_shapes(lib):
         assert rc == _lib.CLOUD_E_INVALID and "brick_log2" in _lib.last_error()
     rc, dense = size(0, (5, 5, 5))                       # dense volumes ignore the shape
     assert rc == _lib.CLOUD_OK and dense == 32 * 20 * 9 * 2
+
+
+def test_tune_keys_checked(lib):
+    ok = lib.cloud_tune
+    try:
+        for key, good, bad in (("supertile", (-1, 0, 4, 64), (-2, 65)),
+                               ("xcd_run", (-1, 0, 16, 65536), (-2, 65537)),
+                               ("taa_tile", (16, 32, 64), (0, 8, 128))):
+            for v in good:
+                assert ok(key.encode(), v) == _lib.CLOUD_OK, (key, v)
+            for v in bad:
+                assert ok(key.encode(), v) == _lib.CLOUD_E_INVALID, (key, v)
+                assert key.encode() in _lib.load().cloud_last_error()
+        assert ok(b"no_such_key", 1) == _lib.CLOUD_E_INVALID
+        assert ok(None, 1) == _lib.CLOUD_E_INVALID
+    finally:
+        ok(b"supertile", -1)
+        ok(b"xcd_run", -1)
+        ok(b"taa_tile", 32)

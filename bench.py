@@ -477,9 +477,6 @@ def main():
                     help="served leg: 1 replays captured graphs, 0 launches kernels one by one")
     ap.add_argument("--no-occupancy", action="store_true",
                     help="render without the exact empty-space-skipping bitmap")
-    ap.add_argument("--no-bounds", action="store_true",
-                    help="render without the volume's stated non-zero box (lookups clamped to "
-                         "the whole volume, packed layouts over the whole volume)")
     ap.add_argument("--serve-poisson", default="",
                     help="comma-separated total arrival rates (req/s): run only the open-loop "
                          "64-stream serving load at each rate and print one JSON line")
@@ -544,8 +541,7 @@ def main():
     dev = torch.device("cuda:0")
     w = scenes.workload(args.workload)
     sc = scenes.make_scene(w, dtype=args.dtype)
-    vol = cf.device_volume(sc, dev, layout=args.layout, occupancy=not args.no_occupancy,
-                           bounds=not args.no_bounds)
+    vol = cf.device_volume(sc, dev, layout=args.layout, occupancy=not args.no_occupancy)
     W, H, p = w.width, w.height, w.params
     if args.jitter_mode is not None:
         from dataclasses import replace
@@ -628,7 +624,7 @@ def main():
     bytes_per_lookup = 8 * elem * (2 if w.detail_n else 1)   # base (+ detail) footprint
     achieved = lk_frame * bytes_per_lookup / (render_ms * 1e-3) / 1e9
     traffic_key = {"workload": w.name, "dtype": args.dtype, "layout": args.layout,
-                   "occupancy": not args.no_occupancy, "bounds": not args.no_bounds}
+                   "occupancy": not args.no_occupancy}
     line = {
         "metric": "Gsamples/s @1080p 8-step+TAA (executed trilinear density lookups per second; "
                   "ms/frame in ms_per_step)",
@@ -650,7 +646,6 @@ def main():
                    "integration": "analytic", "taa_blend": w.taa_blend, "taa": args.taa,
                    "volume": f"{w.volume.n}^3 {args.dtype}", "layout": args.layout,
                    "occupancy_skip": not args.no_occupancy,
-                   "nonzero_bounds": not args.no_bounds,
                    "lookups_per_frame": round(lk_frame),
                    "nominal_lookups_per_frame": V * W * H * p.steps * (1 + p.light_steps)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": MI355X_HBM_GBPS,

@@ -43,7 +43,7 @@ extern "C" {
 /* Raised whenever a struct layout or a signature changes (2: brick_log2 in
  * cloud_volume, queues in cloud_serve_config, depth/trace/ceiling/composite
  * entry points). */
-#define CLOUD_ABI_VERSION 3
+#define CLOUD_ABI_VERSION 2
 
 enum {
   CLOUD_OK = 0,
@@ -60,17 +60,11 @@ enum {
  * replicate each trilinear footprint so that a lookup is one or two aligned
  * fetches instead of eight scattered ones (see cloud_volume_pack).
  *  DENSE  [nz][ny][nx] texels.
- *  QUAD   entries of 4 texels over the corner box [c0, c1] (below): entry
- *         (z', y', x') holds the texels (x, y), (x+1, y), (x, y+1),
- *         (x+1, y+1) of plane z with x = c0x + x' - 1, y = c0y + y' - 1,
- *         z = c0z + z', indices clamped to the volume; c1x - c0x + 2 entries
- *         per row, c1y - c0y + 2 rows and min(c1z + 1, nz - 1) - c0z + 1
- *         planes (nz x (ny+1) x (nx+1) for the whole volume; 4x storage).
- *  OCT    entries of 8 texels: the QUAD entry of plane z - 1 then that of
- *         plane z, z = c0z + z', planes clamped; c1z - c0z + 2 planes of
- *         them ((nz+1) x (ny+1) x (nx+1) for the whole volume; 8x storage).
- *  The corner box is [0, n - 1] per axis unless the volume states bounds
- *  (cloud_volume.bounds_lo/hi): then c0 = max(lo - 1, 0), c1 = min(hi, n - 1).
+ *  QUAD   nz x (ny+1) x (nx+1) entries of 4 texels: entry (z, y', x') holds
+ *         the texels (x, y), (x+1, y), (x, y+1), (x+1, y+1) of plane z with
+ *         x = x'-1, y = y'-1, indices clamped to the volume (4x storage).
+ *  OCT    (nz+1) x (ny+1) x (nx+1) entries of 8 texels: the QUAD entry of
+ *         plane z'-1 then that of plane z' (planes clamped; 8x storage).
  * Packed entries are stored in bricks of 8 entries (one 128-byte line of
  * 16-byte entries): 2^bx x 2^by x 2^bz entries with (bx, by, bz) from
  * cloud_volume.brick_log2 (default 1, 1, 1), x fastest inside a brick, then
@@ -85,7 +79,7 @@ enum { CLOUD_LAYOUT_DENSE = 0, CLOUD_LAYOUT_QUAD = 1, CLOUD_LAYOUT_OCT = 2 };
  * accumulated in float32. */
 enum { CLOUD_F32 = 0, CLOUD_F16 = 1, CLOUD_BF16 = 2 };
 
-/* Density field (Section 1: the density sampled at every step).
+/* Density field (Section 1: "the density is sampled" at each step).
  *  base    device, [nz][ny][nx] values of type dtype, x fastest, y up. Texel
  *          (i,j,k) is centred at box_min + (i+0.5, j+0.5, k+0.5) * extent/n.
  *          Lookups are trilinear (x, then y, then z) with clamp-to-edge.
@@ -109,16 +103,6 @@ enum { CLOUD_F32 = 0, CLOUD_F16 = 1, CLOUD_BF16 = 2 };
  *          each in [0, 3] and summing to 3, or all 0 for (1, 1, 1). A packed
  *          volume must be described with the shape it was packed with
  *          (cloud_volume_pack copies it into the packed descriptor).
- *  bounds_lo, bounds_hi   optional (all 0 = none): a box [lo, hi) of texel
- *          indices per axis outside which every base texel is zero
- *          (cloud_volume_bounds finds the tightest). Lookups are clamped to
- *          the corner box above -- the box widened by one zero texel where it
- *          is not at a face of the volume, beyond which every footprint is
- *          zero -- which changes no result, and a packed layout stores only
- *          the corner box. A packed volume must carry the bounds it was
- *          packed with (cloud_volume_pack copies them). Bounds that leave out
- *          non-zero texels give wrong results but never read outside the
- *          volume. 0 <= lo < hi <= n on every axis.
  *  Requirements: n* >= 2, dn* >= 2 when detail is set, fewer than 2^24
  *  entries per plane, box_max > box_min on every axis,
  *  0 <= detail_weight < 1, detail_tiling > 0, detail values in [0, 1].
@@ -138,8 +122,6 @@ typedef struct {
   const uint32_t* occupancy;
   int32_t occupancy_log2;
   int32_t brick_log2[3];  /* packed layouts: brick shape (see above); all 0 = 1, 1, 1 */
-  int32_t bounds_lo[3];   /* non-zero texel box (see above); all 0 with bounds_hi = none */
-  int32_t bounds_hi[3];
 } cloud_volume;
 
 /* Pinhole camera: rays leave pos through pixel centres; vfov_deg is the
@@ -334,14 +316,6 @@ int cloud_volume_packed_bytes(const cloud_volume* dense, int32_t layout,
  * packed and dense volumes are identical. */
 int cloud_volume_pack(const cloud_volume* dense, int32_t layout, void* dst,
                       uint64_t dst_bytes, cloud_volume* packed, void* hip_stream);
-
-/* Finds the tightest box [lo, hi) per axis holding every non-zero texel of
- * the dense volume's base (an all-zero volume gives [0, 1)) and fills
- * *with_bounds with the volume's descriptor carrying it (see
- * cloud_volume.bounds_lo). Runs a pass over the volume on hip_stream and
- * waits for it; allocates and frees a small device buffer. Returns
- * CLOUD_E_NOMEM if that allocation fails. */
-int cloud_volume_bounds(const cloud_volume* dense, cloud_volume* with_bounds, void* hip_stream);
 
 /* Occupancy bitmap of the dense volume's base, for exact empty-space
  * skipping (see cloud_volume.occupancy). The brick size is the smallest

@@ -23,7 +23,6 @@ from ._lib import (  # noqa: F401
     cloud_composite,
     cloud_taa_resolve,
     cloud_tune,
-    cloud_volume_bounds,
     cloud_volume_occupancy,
     cloud_volume_pack,
     cloud_volume_packed_bytes,
@@ -33,11 +32,10 @@ from ._lib import (  # noqa: F401
 
 
 def device_volume(scene, device="cuda", layout: str = "dense", occupancy: bool = False,
-                  brick=None, bounds: bool = True):
-    """Upload a seeded scene's stored volumes (see scenes.make_scene), with
-    its non-zero texel box stated (unless bounds is False), optionally with an
-    occupancy bitmap, and in a packed layout (entries in bricks of shape
-    `brick`, log2 per axis; None for the default)."""
+                  brick=None):
+    """Upload a seeded scene's stored volumes (see scenes.make_scene),
+    optionally with an occupancy bitmap and in a packed layout (entries in
+    bricks of shape `brick`, log2 per axis; None for the default)."""
     import numpy as np
     import torch
 
@@ -55,8 +53,6 @@ def device_volume(scene, device="cuda", layout: str = "dense", occupancy: bool =
              np.dtype(np.uint16): "bf16"}[scene.base_stored.dtype]
     vol = Volume(base, det, dtype=dtype, detail_weight=w.params.detail_weight,
                  detail_tiling=w.params.detail_tiling)
-    if bounds:
-        vol = cloud_volume_bounds(vol)
     if occupancy:
         vol = cloud_volume_occupancy(vol)
     if layout != "dense":

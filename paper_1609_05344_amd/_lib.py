@@ -40,7 +40,6 @@ class cloud_volume(ctypes.Structure):
         ("ddtype", c_int32), ("detail_weight", c_float), ("detail_tiling", c_float),
         ("box_min", c_float * 3), ("box_max", c_float * 3), ("layout", c_int32),
         ("occupancy", c_void_p), ("occupancy_log2", c_int32), ("brick_log2", c_int32 * 3),
-        ("bounds_lo", c_int32 * 3), ("bounds_hi", c_int32 * 3),
     ]
 
 
@@ -60,7 +59,7 @@ class cloud_params(ctypes.Structure):
 _lib = None
 
 
-ABI_VERSION = 3   # the struct layouts and signatures this binding marshals
+ABI_VERSION = 2   # the struct layouts and signatures this binding marshals
 
 
 def load():
@@ -114,15 +113,13 @@ def load():
                                          POINTER(cloud_params), c_uint32, c_int32, c_int32,
                                          c_void_p, c_int32, c_void_p, c_void_p]
     lib.cloud_volume_packed_bytes.argtypes = [POINTER(cloud_volume), c_int32, POINTER(c_uint64)]
-    lib.cloud_volume_bounds.argtypes = [POINTER(cloud_volume), POINTER(cloud_volume), c_void_p]
     lib.cloud_volume_pack.argtypes = [POINTER(cloud_volume), c_int32, c_void_p, c_uint64,
                                       POINTER(cloud_volume), c_void_p]
     for name in ("cloud_render", "cloud_render_views", "cloud_march_rays", "cloud_taa_resolve",
                  "cloud_jitter_offsets", "cloud_check_buffer", "cloud_count_lookups",
                  "cloud_lookup_trace", "cloud_gather_ceiling", "cloud_render_depth",
                  "cloud_taa_resolve_reproject", "cloud_composite",
-                 "cloud_volume_packed_bytes", "cloud_volume_pack", "cloud_volume_bounds",
-                 "cloud_tune"):
+                 "cloud_volume_packed_bytes", "cloud_volume_pack", "cloud_tune"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -371,21 +368,6 @@ def cloud_volume_pack(volume: Volume, layout: str, stream=None, brick=None) -> "
     out.dense = volume
     out.occupancy = getattr(volume, "occupancy", None)
     out.struct = packed
-    return out
-
-
-def cloud_volume_bounds(volume: Volume, stream=None) -> "Volume":
-    """The same (dense) volume with its non-zero texel box stated (found by a
-    pass over the volume; waits for it). Lookups are then clamped to that box,
-    which changes no result, and a packed copy stores only the box."""
-    st = cloud_volume()
-    check(load().cloud_volume_bounds(ctypes.byref(volume.struct), ctypes.byref(st),
-                                     _stream(stream)))
-    out = Volume.__new__(Volume)
-    out.base, out.detail, out.dtype = volume.base, volume.detail, volume.dtype
-    out.dense = volume
-    out.occupancy = getattr(volume, "occupancy", None)
-    out.struct = st
     return out
 
 

@@ -4,7 +4,6 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
-#include <vector>
 
 #include "../../include/cloud.h"
 #include "cloud_launch.h"
@@ -76,34 +75,16 @@ bool brick_shape(const cloud_volume* v, int b[3]) {
   return b[0] + b[1] + b[2] == 3;
 }
 
-// Corner box [c0, c1] of a volume's lookups (clamp_range per axis); false
-// when the stated non-zero bounds are not a box inside the volume.
-static bool corner_box(const cloud_volume* v, int c0[3], int c1[3]) {
-  const int n[3] = {v->nx, v->ny, v->nz};
-  const bool given = v->bounds_lo[0] || v->bounds_lo[1] || v->bounds_lo[2] || v->bounds_hi[0] ||
-                     v->bounds_hi[1] || v->bounds_hi[2];
-  for (int k = 0; k < 3; ++k) {
-    const int lo = given ? v->bounds_lo[k] : 0, hi = given ? v->bounds_hi[k] : 0;
-    if (given && !(0 <= lo && lo < hi && hi <= n[k])) return false;
-    clamp_range(n[k], lo, hi, &c0[k], &c1[k]);
-  }
-  return true;
-}
-
 int volume_layout_bytes(const cloud_volume* v, int layout, size_t* bytes) {
   if (!v) return fail(CLOUD_E_INVALID, "volume is NULL");
   if (layout < CLOUD_LAYOUT_DENSE || layout > CLOUD_LAYOUT_OCT)
     return fail(CLOUD_E_INVALID, "unknown volume layout");
   if (dtype_size(v->dtype) == 0) return fail(CLOUD_E_INVALID, "unknown volume dtype");
   if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(CLOUD_E_INVALID, "volume dims must be >= 2");
-  int c0[3], c1[3];
-  if (!corner_box(v, c0, c1))
-    return fail(CLOUD_E_INVALID, "bounds must satisfy 0 <= bounds_lo < bounds_hi <= n on every axis");
-  if ((long long)v->nx * v->ny >= (1LL << 24))
-    return fail(CLOUD_E_INVALID, "volume planes must hold < 2^24 texels");
-  // entries (texels, or packed footprints of the corner box) per axis
-  long long ex = v->nx, ey = v->ny, ez = v->nz;
-  if (layout != CLOUD_LAYOUT_DENSE) packed_extent(layout == CLOUD_LAYOUT_OCT, v->nz, c0, c1, &ex, &ey, &ez);
+  // entries (texels, or packed footprints) per plane and in total
+  const long long ex = layout == CLOUD_LAYOUT_DENSE ? v->nx : (long long)v->nx + 1;
+  const long long ey = layout == CLOUD_LAYOUT_DENSE ? v->ny : (long long)v->ny + 1;
+  const long long ez = layout == CLOUD_LAYOUT_OCT ? (long long)v->nz + 1 : v->nz;
   if (ex * ey >= (1LL << 24)) return fail(CLOUD_E_INVALID, "volume planes must hold < 2^24 texels");
   long long row, plane, entries = ex * ey * ez;
   if (layout != CLOUD_LAYOUT_DENSE) {
@@ -155,29 +136,20 @@ int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
   DevVolume d = {};
   d.base = v->base;
   d.nx = v->nx; d.ny = v->ny; d.nz = v->nz;
-  int c0[3], c1[3];
-  corner_box(v, c0, c1);   // validated by volume_layout_bytes
-  for (int k = 0; k < 3; ++k) {
-    d.clo[k] = (float)c0[k];
-    d.chi[k] = (float)c1[k];
-  }
   if (v->layout == CLOUD_LAYOUT_DENSE) {
     d.row = v->nx;
     d.plane = v->nx * v->ny;
   } else {
     int b[3];
     brick_shape(v, b);   // validated by volume_layout_bytes
-    long long ex, ey, ez, row, plane, entries;
-    packed_extent(v->layout == CLOUD_LAYOUT_OCT, v->nz, c0, c1, &ex, &ey, &ez);
-    packed_strides(ex, ey, ez, b[0], b[1], b[2], &row, &plane, &entries);
+    long long row, plane, entries;
+    packed_strides(v->nx + 1, v->ny + 1, v->layout == CLOUD_LAYOUT_OCT ? v->nz + 1 : v->nz, b[0],
+                   b[1], b[2], &row, &plane, &entries);
     d.row = (int)row;
     d.plane = (int)plane;
     d.bx = b[0];
     d.by = b[1];
     d.bz = b[2];
-    d.eo[0] = 1 - c0[0];
-    d.eo[1] = 1 - c0[1];
-    d.eo[2] = v->layout == CLOUD_LAYOUT_OCT ? 1 - c0[2] : -c0[2];
   }
   const int n[3] = {v->nx, v->ny, v->nz};
   float* s[3] = {&d.sx, &d.sy, &d.sz};
@@ -531,11 +503,10 @@ int cloud_volume_pack(const cloud_volume* dense, int32_t layout, void* dst, uint
     if (d0 < t0 + tbytes && t0 < d0 + need) return fail(CLOUD_E_INVALID, "dst overlaps the detail volume");
   }
   const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  int brick[3], c0[3], c1[3];
+  int brick[3];
   brick_shape(dense, brick);   // validated by packed_bytes
-  corner_box(dense, c0, c1);
   hipError_t e = launch_pack(dense->base, (int)es, dense->nx, dense->ny, dense->nz, layout, brick,
-                             c0, c1, dst, s);
+                             dst, s);
   if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("pack launch: ") + hipGetErrorString(e));
   void* ddst = nullptr;
   if (dense->detail) {
@@ -704,51 +675,6 @@ int cloud_volume_occupancy_bytes(const cloud_volume* dense, uint64_t* bytes, int
   occupancy_dims(dense, lg, &nbx, &nby, &nbz);
   *bytes = (uint64_t)occupancy_words(nbx, nby, nbz) * 4;
   *log2_brick = lg;
-  return CLOUD_OK;
-  CLOUD_GUARD_END
-}
-
-int cloud_volume_bounds(const cloud_volume* dense, cloud_volume* with_bounds, void* hip_stream) {
-  CLOUD_GUARD_BEGIN
-  clear_error();
-  if (!dense) return fail(CLOUD_E_INVALID, "volume is NULL");
-  if (!with_bounds) return fail(CLOUD_E_INVALID, "with_bounds is NULL");
-  if (dense->layout != CLOUD_LAYOUT_DENSE) return fail(CLOUD_E_INVALID, "source volume must be dense");
-  cloud_volume src = *dense;
-  for (int k = 0; k < 3; ++k) src.bounds_lo[k] = src.bounds_hi[k] = 0;
-  src.occupancy = nullptr;
-  DevVolume v;
-  int dtype, rc;
-  if ((rc = prepare_volume(&src, &v, &dtype))) return rc;
-  const int n[3] = {dense->nx, dense->ny, dense->nz};
-  const int words = n[0] + n[1] + n[2];
-  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  uint32_t* flags = nullptr;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&flags), (size_t)words * 4);
-  if (e == hipErrorOutOfMemory) return fail(CLOUD_E_NOMEM, "bounds: out of device memory");
-  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("bounds: ") + hipGetErrorString(e));
-  std::vector<uint32_t> h((size_t)words, 0u);
-  e = launch_extent(dense->base, (int)dtype_size(dtype), n[0], n[1], n[2], flags, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(h.data(), flags, (size_t)words * 4, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  const hipError_t ef = hipFree(flags);
-  if (e == hipSuccess) e = ef;
-  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("bounds: ") + hipGetErrorString(e));
-  *with_bounds = *dense;
-  const uint32_t* f = h.data();
-  for (int k = 0; k < 3; ++k) {
-    int lo = -1, hi = -1;
-    for (int i = 0; i < n[k]; ++i)
-      if (f[i]) {
-        if (lo < 0) lo = i;
-        hi = i + 1;
-      }
-    // an all-zero volume: the first texel along each axis (zero) as the box
-    with_bounds->bounds_lo[k] = lo < 0 ? 0 : lo;
-    with_bounds->bounds_hi[k] = lo < 0 ? 1 : hi;
-    f += n[k];
-  }
   return CLOUD_OK;
   CLOUD_GUARD_END
 }

@@ -16,9 +16,9 @@ __device__ __forceinline__ uint32_t raw_lookup(const DevVolume& v, float fx, flo
   using S = BaseSampler<DT, LAYOUT>;
   float wx, wy, wz;
   int kx, ky, kz;
-  split_coord(fx, v.clo[0], v.chi[0], wx, kx);
-  split_coord(fy, v.clo[1], v.chi[1], wy, ky);
-  split_coord(fz, v.clo[2], v.chi[2], wz, kz);
+  split_coord(fx, v.nx, wx, kx);
+  split_coord(fy, v.ny, wy, ky);
+  split_coord(fz, v.nz, wz, kz);
   const bool live = OCC ? occupied(v, kx, ky, kz) : true;
 #if !CLOUD_OCC_SELECT
   if (!live) return 0u;

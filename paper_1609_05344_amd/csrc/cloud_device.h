@@ -114,18 +114,17 @@ __device__ __forceinline__ void unpack2(uint32_t u, float& lo, float& hi) {
 
 __device__ __forceinline__ float lerp(float a, float b, float w) { return fmaf(w, b - a, a); }
 
-// Continuous texel coordinate bounded to the clamp range [lo, hi] (integers
-// within [0, n - 1]; see clamp_range), split into the corner k and the weight
-// w. Under clamp-to-edge a lookup is constant beyond the outer texel centres,
-// and at a bound w = 0 selects the texel there exactly, so the bound changes
-// no lookup; it keeps k inside [lo, hi] for any input (NaN too), which the
-// index arithmetic below relies on. The clamp is one median-of-three (a NaN
-// input gives lo); f >= 0 then, so the fraction is f - floor(f) exactly and
-// truncation is the floor.
-__device__ __forceinline__ void split_coord(float f, float lo, float hi, float& w, int& k) {
-  f = __builtin_amdgcn_fmed3f(f, lo, hi);
+// Continuous texel coordinate bounded to [0, n - 1], split into the corner k
+// and the weight w. Under clamp-to-edge a lookup is constant beyond the outer
+// texel centres, and at the bound w = 0 selects the edge texel exactly, so the
+// bound changes no lookup; it keeps k inside [0, n - 1] for any input (NaN
+// too), which the index arithmetic below relies on.
+// The clamp is one median-of-three (a NaN input gives 0); f >= 0 then, so
+// the fraction is f - floor(f) exactly and truncation is the floor.
+__device__ __forceinline__ void split_coord(float f, int n, float& w, int& k) {
+  f = __builtin_amdgcn_fmed3f(f, 0.0f, (float)(n - 1));
   w = __builtin_amdgcn_fractf(f);
-  k = (int)f;   // in [lo, hi]
+  k = (int)f;   // in [0, n - 1]
 }
 
 // ---------------------------------------------------------------------------
@@ -205,10 +204,10 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
   }
 };
 
-// Entry of the footprint with corner k (kx, ky in the clamp range) in packed
-// plane z (already offset) of a packed volume.
+// Entry of the footprint with corner k (kx, ky in [0, n - 1]) in packed
+// plane z of a packed volume.
 __device__ __forceinline__ int packed_entry(const DevVolume& v, int kx, int ky, int z) {
-  return packed_index(kx + v.eo[0], ky + v.eo[1], z, v.bx, v.by, v.bz, v.row, v.plane);
+  return packed_index(kx + 1, ky + 1, z, v.bx, v.by, v.bz, v.row, v.plane);
 }
 
 // Four float32 texels, or eight 16-bit texels packed two to a word (low half
@@ -233,7 +232,7 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
-    const int za = kz + v.eo[2], zb = min(kz + 1, v.nz - 1) + v.eo[2];
+    const int za = kz, zb = min(kz + 1, v.nz - 1);
     const int ia = packed_entry(v, kx, ky, za), ib = packed_entry(v, kx, ky, zb);
     const int ea = live ? ia : 0;
     const int eb = live ? ib : 0;
@@ -267,7 +266,7 @@ struct BaseSampler<DT, LAYOUT_OCT> {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
-    const int ie = packed_entry(v, kx, ky, kz + v.eo[2]);
+    const int ie = packed_entry(v, kx, ky, kz + 1);
     const int e = live ? ie : 0;
     if constexpr (DT == DT_F32) {
       const uint4* q = static_cast<const uint4*>(v.base) + 2 * (size_t)(uint32_t)e;
@@ -294,9 +293,9 @@ __device__ __forceinline__ float base_lookup(const DevVolume& v, float fx, float
   using S = BaseSampler<DT, LAYOUT>;
   float wx, wy, wz;
   int kx, ky, kz;
-  split_coord(fx, v.clo[0], v.chi[0], wx, kx);
-  split_coord(fy, v.clo[1], v.chi[1], wy, ky);
-  split_coord(fz, v.clo[2], v.chi[2], wz, kz);
+  split_coord(fx, v.nx, wx, kx);
+  split_coord(fy, v.ny, wy, ky);
+  split_coord(fz, v.nz, wz, kz);
   const bool live = occupied(v, kx, ky, kz);
   CLOUD_SKIP_DEAD(live);
   uint32_t w[S::kWords];

@@ -69,16 +69,9 @@ hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParam
                        long long n, float* out, hipStream_t s);
 
 // Pack a dense [nz][ny][nx] volume of 2- or 4-byte texels into a quad or oct
-// layout at dst over the corner box [c0, c1] (see clamp_range), entries in
-// bricks of brick[0..2] (log2 per axis).
+// layout at dst, entries in bricks of brick[0..2] (log2 per axis).
 hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,
-                       const int* brick, const int* c0, const int* c1, void* dst, hipStream_t s);
-
-// Set flags[x], flags[nx + y] and flags[nx + ny + z] to 1 for every non-zero
-// texel (x, y, z) of a dense volume (flags: nx + ny + nz words, zeroed here
-// first).
-hipError_t launch_extent(const void* src, int elem_bytes, int nx, int ny, int nz, uint32_t* flags,
-                         hipStream_t s);
+                       const int* brick, void* dst, hipStream_t s);
 
 // Pack a dense repeat-addressed detail volume into its oct-wrap layout.
 hipError_t launch_pack_detail(const void* src, int elem_bytes, int nx, int ny, int nz, void* dst,

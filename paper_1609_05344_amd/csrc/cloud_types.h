@@ -55,41 +55,12 @@ inline __host__ __device__ void packed_strides(long long ex, long long ey, long 
   *entries = nbx * nby * nbz * 8;
 }
 
-// Corner range [c0, c1] that lookups along an axis of n texels are clamped
-// to, for a volume whose non-zero texels lie in [lo, hi) on that axis
-// (lo = hi = 0: not stated, the whole axis). One zero texel of margin is kept
-// on each side that is not a face of the volume: beyond the margin every
-// footprint is zero, and at the margin the weight is 0 and the texel is zero,
-// so the clamp changes no lookup.
-inline __host__ __device__ void clamp_range(int n, int lo, int hi, int* c0, int* c1) {
-  if (lo == 0 && hi == 0) {
-    *c0 = 0;
-    *c1 = n - 1;
-    return;
-  }
-  *c0 = lo > 0 ? lo - 1 : 0;
-  *c1 = hi < n ? hi : n - 1;
-}
-
-// Entries along each axis of a packed layout of the corner box [c0, c1]:
-// entry e holds corner c0 + e - 1 (entry 0, below the box, is where dead
-// lookups point); the quad layout has one plane per z it reads, c0z to
-// min(c1z + 1, nz - 1).
-inline __host__ __device__ void packed_extent(bool oct, int nz, const int c0[3], const int c1[3],
-                                              long long* ex, long long* ey, long long* ez) {
-  *ex = (long long)c1[0] - c0[0] + 2;
-  *ey = (long long)c1[1] - c0[1] + 2;
-  *ez = oct ? (long long)c1[2] - c0[2] + 2 : (long long)min(c1[2] + 1, nz - 1) - c0[2] + 1;
-}
-
 struct DevVolume {
   const void* base;
   int nx, ny, nz;
   int plane;            // dense: nx * ny; packed: the plane stride of packed_index
   int row;              // dense: nx; packed: the row stride of packed_index
   int bx, by, bz;       // packed: brick shifts of packed_index
-  float clo[3], chi[3]; // lookups clamp continuous texel coordinates to [clo, chi]
-  int eo[3];            // packed: entry of corner k along an axis is k + eo (z: plane)
   // continuous texel coordinate along each axis: f = p * s + o, texel k's
   // centre at f = k (texel centres at box_min + (k + 0.5) * extent / n)
   float sx, sy, sz, ox, oy, oz;

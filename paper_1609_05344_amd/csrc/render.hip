@@ -2,7 +2,6 @@
 // kernels, and their launchers.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <mutex>
 
 #include "cloud_device.h"
@@ -115,23 +114,22 @@ __global__ __launch_bounds__(256) void rays_kernel(DevVolume vol, DevParams prm,
 }
 
 // ---------------------------------------------------------------------------
-// Volume packing over the corner box [c0, c1]: entry (z', y', x') of a
-// packed layout holds the texels of the corner k = c0 + (x'-1, y'-1, z'-1)
-// and its +1 neighbours, edge-clamped (quad: x and y only, plane
-// z = c0z + z'). Storage values are copied bit for bit.
+// Volume packing: entry (z', y', x') of a packed layout holds the texels of
+// the corner k = (x'-1, y'-1, z'-1) and its +1 neighbours, edge-clamped
+// (quad: x and y only, plane z = z'). Storage values are copied bit for bit.
 // ---------------------------------------------------------------------------
 
 template <typename E, int CORNERS>
 __global__ __launch_bounds__(256) void pack_kernel(const E* __restrict__ src, int nx, int ny,
-                                                   int nz, int ex, int ey, int ez, int c0x,
-                                                   int c0y, int c0z, int bx, int by, int bz,
+                                                   int nz, int ez, int bx, int by, int bz,
                                                    int row, int plane, E* __restrict__ dst) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)ex * ey * ez) return;
-  const int ix = (int)(e % ex), iy = (int)((e / ex) % ey), iz = (int)(e / ((long long)ex * ey));
-  const int x = c0x + ix - 1;
-  const int y = c0y + iy - 1;
-  const int z = c0z + iz - (CORNERS == 8 ? 1 : 0);
+  const long long ex = nx + 1, ey = ny + 1;
+  if (e >= ex * ey * ez) return;
+  const int ix = (int)(e % ex), iy = (int)((e / ex) % ey), iz = (int)(e / (ex * ey));
+  const int x = ix - 1;
+  const int y = iy - 1;
+  const int z = iz - (CORNERS == 8 ? 1 : 0);
   const int xa = min(max(x, 0), nx - 1), xb = min(max(x + 1, 0), nx - 1);
   const int ya = min(max(y, 0), ny - 1), yb = min(max(y + 1, 0), ny - 1);
   const int za = min(max(z, 0), nz - 1), zb = min(max(z + 1, 0), nz - 1);
@@ -201,22 +199,6 @@ __global__ __launch_bounds__(256) void occupancy_kernel(const E* __restrict__ sr
           break;
         }
   if (any) atomicOr(&out[b >> 5], 1u << (b & 31));
-}
-
-template <typename E>
-__global__ __launch_bounds__(256) void extent_kernel(const E* __restrict__ src, int nx, int ny,
-                                                     int nz, E magnitude_mask,
-                                                     uint32_t* __restrict__ flags) {
-  const long long n = (long long)nx * ny * nz;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    if (src[i] & magnitude_mask) {
-      const long long r = i / nx;
-      flags[i - r * nx] = 1u;
-      flags[nx + (int)(r % ny)] = 1u;
-      flags[nx + ny + (int)(r / ny)] = 1u;
-    }
-  }
 }
 
 __global__ __launch_bounds__(256) void jitter_kernel(const uint32_t* __restrict__ pxy, long long n,
@@ -404,36 +386,30 @@ hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParam
 }
 
 hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,
-                       const int* brick, const int* c0, const int* c1, void* dst, hipStream_t s) {
-  long long lx, ly, lz;
-  packed_extent(layout == LAYOUT_OCT, nz, c0, c1, &lx, &ly, &lz);
-  const int ex = (int)lx, ey = (int)ly, ez = (int)lz;
-  const long long entries = lx * ly * lz;
+                       const int* brick, void* dst, hipStream_t s) {
+  const int ez = layout == LAYOUT_OCT ? nz + 1 : nz;
+  const long long entries = (long long)(nx + 1) * (ny + 1) * ez;
   const unsigned blocks = (unsigned)((entries + 255) / 256);
   long long row, plane, stored;
   const int bx = brick[0], by = brick[1], bz = brick[2];
-  packed_strides(ex, ey, ez, bx, by, bz, &row, &plane, &stored);
+  packed_strides(nx + 1, ny + 1, ez, bx, by, bz, &row, &plane, &stored);
   if (elem_bytes == 4) {
     if (layout == LAYOUT_OCT)
       hipLaunchKernelGGL((pack_kernel<uint32_t, 8>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint32_t*>(src), nx, ny, nz, ex, ey, ez, c0[0], c0[1], c0[2], bx, by, bz,
-                         (int)row, (int)plane,
+                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, bx, by, bz, (int)row, (int)plane,
                          static_cast<uint32_t*>(dst));
     else
       hipLaunchKernelGGL((pack_kernel<uint32_t, 4>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint32_t*>(src), nx, ny, nz, ex, ey, ez, c0[0], c0[1], c0[2], bx, by, bz,
-                         (int)row, (int)plane,
+                         static_cast<const uint32_t*>(src), nx, ny, nz, ez, bx, by, bz, (int)row, (int)plane,
                          static_cast<uint32_t*>(dst));
   } else {
     if (layout == LAYOUT_OCT)
       hipLaunchKernelGGL((pack_kernel<uint16_t, 8>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(src), nx, ny, nz, ex, ey, ez, c0[0], c0[1], c0[2], bx, by, bz,
-                         (int)row, (int)plane,
+                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, bx, by, bz, (int)row, (int)plane,
                          static_cast<uint16_t*>(dst));
     else
       hipLaunchKernelGGL((pack_kernel<uint16_t, 4>), dim3(blocks), dim3(256), 0, s,
-                         static_cast<const uint16_t*>(src), nx, ny, nz, ex, ey, ez, c0[0], c0[1], c0[2], bx, by, bz,
-                         (int)row, (int)plane,
+                         static_cast<const uint16_t*>(src), nx, ny, nz, ez, bx, by, bz, (int)row, (int)plane,
                          static_cast<uint16_t*>(dst));
   }
   return hipGetLastError();
@@ -467,23 +443,6 @@ hipError_t launch_occupancy(const void* src, int elem_bytes, int nx, int ny, int
     hipLaunchKernelGGL((occupancy_kernel<uint16_t>), dim3(blocks), dim3(256), 0, s,
                        static_cast<const uint16_t*>(src), nx, ny, nz, lg, nbx, nby, nbz,
                        (uint16_t)0x7FFFu, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_extent(const void* src, int elem_bytes, int nx, int ny, int nz, uint32_t* flags,
-                         hipStream_t s) {
-  const int words = nx + ny + nz;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3((words + 255) / 256), dim3(256), 0, s, flags, words);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const long long n = (long long)nx * ny * nz;
-  const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 16384);
-  if (elem_bytes == 4)
-    hipLaunchKernelGGL((extent_kernel<uint32_t>), dim3(blocks), dim3(256), 0, s,
-                       static_cast<const uint32_t*>(src), nx, ny, nz, (uint32_t)0x7FFFFFFFu, flags);
-  else
-    hipLaunchKernelGGL((extent_kernel<uint16_t>), dim3(blocks), dim3(256), 0, s,
-                       static_cast<const uint16_t*>(src), nx, ny, nz, (uint16_t)0x7FFFu, flags);
   return hipGetLastError();
 }
 

@@ -37,18 +37,17 @@ def test_exports_every_declared_function(lib):
     assert len(names) >= 6
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.cloud_abi_version() == _lib.ABI_VERSION == 3
+    assert lib.cloud_abi_version() == _lib.ABI_VERSION == 2
 
 
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "cloud.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cloud_volume),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cloud_volume),"
         " sizeof(cloud_camera), sizeof(cloud_params), offsetof(cloud_volume, layout),"
         " offsetof(cloud_params, t_eps), offsetof(cloud_volume, detail),"
-        " sizeof(cloud_serve_config), offsetof(cloud_serve_config, queues),"
-        " offsetof(cloud_volume, bounds_hi));return 0;}\n")
+        " sizeof(cloud_serve_config), offsetof(cloud_serve_config, queues));return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True)
@@ -57,8 +56,7 @@ def test_struct_layout_matches_header(tmp_path):
     assert got == [ctypes.sizeof(_lib.cloud_volume), ctypes.sizeof(_lib.cloud_camera),
                    ctypes.sizeof(_lib.cloud_params), _lib.cloud_volume.layout.offset,
                    _lib.cloud_params.t_eps.offset, _lib.cloud_volume.detail.offset,
-                   ctypes.sizeof(_lib.cloud_serve_config), _lib.cloud_serve_config.queues.offset,
-                   _lib.cloud_volume.bounds_hi.offset]
+                   ctypes.sizeof(_lib.cloud_serve_config), _lib.cloud_serve_config.queues.offset]
 
 
 def test_argument_errors_before_any_launch(lib):
@@ -117,39 +115,6 @@ def test_packed_bytes_and_brick_shapes(lib):
         assert rc == _lib.CLOUD_E_INVALID and "brick_log2" in _lib.last_error()
     rc, dense = size(0, (5, 5, 5))                       # dense volumes ignore the shape
     assert rc == _lib.CLOUD_OK and dense == 32 * 20 * 9 * 2
-
-
-def test_packed_bytes_with_bounds(lib):
-    # stated non-zero bounds [lo, hi): the packed layout covers the corner box
-    # [max(lo - 1, 0), min(hi, n - 1)] (one zero texel of margin inside the
-    # volume), plus the dead entry below it; the quad layout keeps one plane
-    # more above the box where there is one
-    vol = _lib.cloud_volume()
-    vol.nx, vol.ny, vol.nz, vol.dtype = 32, 20, 9, 0       # f32
-    n = ctypes.c_uint64(0)
-
-    def size(layout, lo, hi):
-        vol.bounds_lo[:], vol.bounds_hi[:] = list(lo), list(hi)
-        rc = lib.cloud_volume_packed_bytes(ctypes.byref(vol), layout, ctypes.byref(n))
-        return rc, int(n.value)
-
-    def up(e):
-        return -(-e // 2) * 2                                # default 2 x 2 x 2 bricks
-
-    for lo, hi in (((0, 0, 0), (32, 20, 9)), ((5, 3, 2), (17, 20, 6)), ((0, 7, 8), (1, 8, 9))):
-        c0 = [max(a - 1, 0) for a in lo]
-        c1 = [min(b, m - 1) for b, m in zip(hi, (32, 20, 9))]
-        ex, ey = c1[0] - c0[0] + 2, c1[1] - c0[1] + 2
-        for layout, ez, corners in ((1, min(c1[2] + 1, 8) - c0[2] + 1, 4), (2, c1[2] - c0[2] + 2, 8)):
-            rc, got = size(layout, lo, hi)
-            assert rc == _lib.CLOUD_OK
-            assert got == up(ex) * up(ey) * up(ez) * corners * 4, (lo, hi, layout)
-    # no bounds is the whole volume
-    assert size(2, (0, 0, 0), (0, 0, 0)) == size(2, (0, 0, 0), (32, 20, 9))
-    for lo, hi in (((0, 0, 0), (33, 20, 9)), ((4, 0, 0), (4, 20, 9)), ((-1, 0, 0), (5, 5, 5)),
-                   ((0, 0, 3), (32, 20, 2))):
-        rc, _ = size(1, lo, hi)
-        assert rc == _lib.CLOUD_E_INVALID and "bounds" in _lib.last_error()
 
 
 def test_tune_keys_checked(lib):

@@ -208,103 +208,3 @@ def test_packed_detail_matches_dense_and_oracle(cf, dtype):
         assert np.array_equal(to_np(cf.cloud_render(v, cam, w.params, 2, 64, 48)), dense)
     tol = FP32_TOL if dtype == "f32" else HALF_TOL
     assert max_err(dense, O.render(oracle_volume(sc), cam, w.params, 64, 48, frame=2)) < tol
-
-
-# ---------------------------------------------------------------------------
-# stated non-zero bounds: clamp to the box (exact) and pack only the box
-# ---------------------------------------------------------------------------
-
-def nonzero_box(base):
-    """[lo, hi) per axis (x, y, z) of the non-zero texels; [0, 1) when none."""
-    nz = np.nonzero(base)
-    if len(nz[0]) == 0:
-        return [0, 0, 0], [1, 1, 1]
-    lo = [int(nz[2].min()), int(nz[1].min()), int(nz[0].min())]
-    hi = [int(nz[2].max()) + 1, int(nz[1].max()) + 1, int(nz[0].max()) + 1]
-    return lo, hi
-
-
-def sparse_scene(shape, box, seed):
-    """A random volume that is zero outside box = ((x0, x1), (y0, y1), (z0, z1))."""
-    nx, ny, nz = shape
-    rng = np.random.default_rng(seed)
-    base = np.zeros((nz, ny, nx))
-    (x0, x1), (y0, y1), (z0, z1) = box
-    base[z0:z1, y0:y1, x0:x1] = np.clip(rng.uniform(-0.2, 1.0, size=(z1 - z0, y1 - y0, x1 - x0)), 0, 1)
-    st = scenes.quantise(base, "f32")
-    return scenes.Scene(scenes.workload("C1", jitter=1), st, scenes.decode(st, "f32"))
-
-
-@pytest.mark.parametrize("case", ["H", "C1", "inner", "faces", "single", "empty"])
-def test_bounds_match_nonzero_box(cf, case):
-    say(f"bounds of {case}")
-    if case in ("H", "C1"):
-        sc = scenes.make_scene(scenes.workload(case))
-    elif case == "inner":
-        sc = sparse_scene((40, 33, 21), ((5, 30), (9, 20), (3, 17)), 1)
-    elif case == "faces":
-        sc = sparse_scene((40, 33, 21), ((0, 40), (9, 33), (0, 10)), 2)
-    elif case == "single":
-        sc = sparse_scene((12, 10, 9), ((7, 8), (0, 1), (8, 9)), 3)
-    else:
-        sc = sparse_scene((12, 10, 9), ((0, 0), (0, 0), (0, 0)), 4)
-    vol = cf.device_volume(sc)
-    lo, hi = nonzero_box(sc.base_stored)
-    assert list(vol.struct.bounds_lo) == lo and list(vol.struct.bounds_hi) == hi
-    if case == "H":
-        assert hi[1] - lo[1] < 0.75 * 256      # the slab layer leaves a quarter of y empty
-
-
-@pytest.mark.parametrize("dtype", ["f32", "f16"])
-@pytest.mark.parametrize("layout", ["dense", "quad", "oct"])
-def test_bounds_change_no_result(cf, dtype, layout):
-    say(f"bounds vs none, {layout} {dtype}: H frames and sparse volumes bitwise; packed size shrinks")
-    import torch
-    w = scenes.workload("H")
-    sc = scenes.make_scene(w, dtype=dtype)
-    full = cf.device_volume(sc, layout=layout, occupancy=True, bounds=False)
-    cut = cf.device_volume(sc, layout=layout, occupancy=True)
-    for f in (2, 9):
-        a = to_np(cf.cloud_render(full, w.camera(f), w.params, f, 640, 360))
-        b = to_np(cf.cloud_render(cut, w.camera(f), w.params, f, 640, 360))
-        assert np.array_equal(a, b)
-        assert a[..., 3].max() > 0.3
-    if layout != "dense":
-        assert cut.base.numel() < 0.8 * full.base.numel()
-    # boxes inside the volume, touching faces, a single texel, and none; from
-    # inside the volume too, and with the counting pass
-    c1 = scenes.workload("C1", jitter=1)
-    for i, box in enumerate((((5, 30), (9, 20), (3, 17)), ((0, 40), (9, 33), (0, 10)),
-                             ((17, 18), (2, 3), (20, 21)), ((0, 0), (0, 0), (0, 0)))):
-        ss = sparse_scene((40, 33, 21), box, 10 + i)
-        if dtype == "f16":
-            st = scenes.quantise(ss.base_f64, "f16")
-            ss = scenes.Scene(ss.workload, st, scenes.decode(st, "f16"))
-        vf = cf.device_volume(ss, layout=layout, occupancy=layout != "dense", bounds=False)
-        vc = cf.device_volume(ss, layout=layout, occupancy=layout != "dense")
-        for cam in (scenes.orbit_camera(1.6, 205.0, 30.0), scenes.orbit_camera(0.2, 40.0, -10.0)):
-            a = to_np(cf.cloud_render(vf, cam, c1.params, 1, 48, 40))
-            b = to_np(cf.cloud_render(vc, cam, c1.params, 1, 48, 40))
-            assert np.array_equal(a, b), box
-            na = int(cf.cloud_count_lookups(vf, cam, c1.params, 1, 48, 40).cpu()[0])
-            nb = int(cf.cloud_count_lookups(vc, cam, c1.params, 1, 48, 40).cpu()[0])
-            assert na == nb, box
-    torch.cuda.synchronize()
-
-
-def test_bounds_with_detail(cf):
-    say("bounds vs none: C3 with detail, oct f16, sampled frame bitwise")
-    w = scenes.workload("C3")
-    sc = scenes.make_scene(w)
-    # zero the lower third of the base so that the box is smaller than the volume
-    base = sc.base_f64.copy()
-    base[:, :40, :] = 0.0
-    st = scenes.quantise(base, "f16")
-    sc = scenes.Scene(w, st, scenes.decode(st, "f16"), sc.detail_stored, sc.detail_f64)
-    for layout in ("dense", "oct"):
-        a = to_np(cf.cloud_render(cf.device_volume(sc, layout=layout, bounds=False), w.camera(1),
-                                  w.params, 1, 480, 270))
-        b = to_np(cf.cloud_render(cf.device_volume(sc, layout=layout), w.camera(1), w.params, 1,
-                                  480, 270))
-        assert np.array_equal(a, b)
-        assert a[..., 3].max() > 0.3

@@ -153,8 +153,8 @@ typedef struct {
  *               Section 5 leaves to future work).
  *  integration  1: analytic, S += T L_in (1 - exp(-rho alpha D)) (Section 3.1);
  *               0: the basic rule, T updated first, S += T rho alpha D L_in.
- *  t_eps        stop a ray once T < t_eps ("until the alpha reaches 1",
- *               Section 1); 0 disables the early exit. */
+ *  t_eps        stop a ray once T < t_eps (the march ends once the alpha is
+ *               full, Section 1); 0 disables the early exit. */
 typedef struct {
   int32_t steps;
   int32_t light_steps;

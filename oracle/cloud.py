@@ -26,7 +26,8 @@ the function that applies it):
 * R10 Texel centres at (k + 0.5)/n, clamp-to-edge for the base volume,
       repeat for the detail volume, lerps in x, then y, then z as a + w (b - a).
 * R11 Detail erosion rho = clamp((b - w_e d) / (1 - w_e d), 0, 1).
-* R12 "Until alpha reaches 1" is T < t_eps after the step's update.
+* R12 The march ending once the accumulated alpha is full is T < t_eps after
+      the step's update.
 * R13 Temporal resolve: per-channel 3x3 min/max clamp of the history, then
       out = h + beta (cur - h); frame 0 (or no history) copies the current frame.
 * R14 The random offset is a PCG hash chain (Jarzynski and Olano 2020) of the
@@ -133,7 +134,7 @@ def hg_phase(mu, g: float):
 
 
 # ---------------------------------------------------------------------------
-# Rays (Section 1: rays are fired into the volume; reading R16)
+# Rays (Section 1: one ray per pixel into the volume; reading R16)
 # ---------------------------------------------------------------------------
 
 def _normalize(v):
@@ -162,8 +163,8 @@ def ray_box(o, d, box_min, box_max):
     """Slab test; returns (t_near, t_far, hit) with t_near clamped at 0.
 
     An axis with d_k = 0 passes when box_min_k <= o_k <= box_max_k and fails
-    otherwise. The ray misses when t_far <= t_near (Section 1: the march runs
-    until the ray reaches the end of the volume)."""
+    otherwise. The ray misses when t_far <= t_near (Section 1: the march ends
+    where the ray leaves the volume)."""
     o = np.asarray(o, dtype=np.float64)
     d = np.asarray(d, dtype=np.float64)
     n = o.shape[0]

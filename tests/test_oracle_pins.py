@@ -55,7 +55,7 @@ def test_hg_spot_values():
 
 
 # ---------------------------------------------------------------------------
-# Rays and the box (Section 1: rays fired into the volume, march to its end)
+# Rays and the box (Section 1: one ray per pixel, marched to where it leaves the volume)
 # ---------------------------------------------------------------------------
 
 def test_camera_single_pixel_looks_at_target():

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void gather_ceiling_kernel(DevVolume vol, DevP
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int px, py;
   tile_pixel(tx, ty, wave, lane, px, py);
-  stage_occupancy(vol);
+  stage_volume<LAYOUT>(vol);
   if (px >= W || py >= H) return;
   const size_t pix = ((size_t)view * H + py) * W + px;
   const uint2 tr = trace[pix];
@@ -144,6 +144,12 @@ static hipError_t ceiling_layout(int layout, const DevVolume& v, const DevParams
       return ceiling_run<DT, LAYOUT_QUAD>(v, p, c, n_views, frame, W, H, trace, random, out, s);
     case LAYOUT_OCT:
       return ceiling_run<DT, LAYOUT_OCT>(v, p, c, n_views, frame, W, H, trace, random, out, s);
+    case LAYOUT_QUAD | kLayoutTab:
+      return ceiling_run<DT, LAYOUT_QUAD | kLayoutTab>(v, p, c, n_views, frame, W, H, trace, random,
+                                                       out, s);
+    case LAYOUT_OCT | kLayoutTab:
+      return ceiling_run<DT, LAYOUT_OCT | kLayoutTab>(v, p, c, n_views, frame, W, H, trace, random,
+                                                      out, s);
     default:
       return ceiling_run<DT, LAYOUT_DENSE>(v, p, c, n_views, frame, W, H, trace, random, out, s);
   }
@@ -152,6 +158,7 @@ static hipError_t ceiling_layout(int layout, const DevVolume& v, const DevParams
 hipError_t launch_ceiling(const DevVolume& v, int dtype, int layout, const DevParams& p,
                           const DevCameras& c, int n_views, uint32_t frame, int W, int H,
                           const uint32_t* trace, bool random, float* out, hipStream_t s) {
+  layout = sampler_layout(v, layout);
   switch (dtype) {
     case DT_F16:
       return ceiling_layout<DT_F16>(layout, v, p, c, n_views, frame, W, H, trace, random, out, s);

@@ -133,11 +133,32 @@ __device__ __forceinline__ void split_coord(float f, int n, float& w, int& k) {
 
 static __shared__ uint32_t s_occupancy[kOccupancyWords];
 
-// Copies the volume's occupancy bitmap (if any) into LDS. Every thread of the
-// workgroup must call it before sampling (it ends with a barrier).
-__device__ __forceinline__ void stage_occupancy(const DevVolume& v) {
+// Entry-index terms of a table-indexed packed volume (kLayoutTab): entry
+// (x + 1, y + 1, z) of packed_index is s_terms[x] + s_terms[kTabAxis + y] +
+// s_terms[2 kTabAxis + z], for corners x, y and packed planes z.
+static __shared__ int s_terms[3 * kTabAxis];
+
+__device__ __forceinline__ int packed_term(int i, int sh, int stride, int low_shift) {
+  return (mul24(i >> sh, stride) << 3) | ((i & ((1 << sh) - 1)) << low_shift);
+}
+
+// Copies the volume's occupancy bitmap (if any) into LDS and, for a
+// table-indexed packed layout, builds the entry-index terms there. Every
+// thread of the workgroup must call it before sampling (it ends with a
+// barrier).
+template <int LAYOUT>
+__device__ __forceinline__ void stage_volume(const DevVolume& v) {
   if (v.occ) {
     for (int i = threadIdx.x; i < v.occ_words; i += blockDim.x) s_occupancy[i] = v.occ[i];
+  }
+  if constexpr ((LAYOUT & kLayoutTab) != 0) {
+    // packed planes: 0..nz-1 (quad), 0..nz (oct); the host checked tab_fits
+    const int planes = (LAYOUT & 3) == LAYOUT_OCT ? v.nz + 1 : v.nz;
+    for (int i = threadIdx.x; i < v.nx; i += blockDim.x) s_terms[i] = packed_term(i + 1, v.bx, 1, 0);
+    for (int i = threadIdx.x; i < v.ny; i += blockDim.x)
+      s_terms[kTabAxis + i] = packed_term(i + 1, v.by, v.row, v.bx);
+    for (int i = threadIdx.x; i < planes; i += blockDim.x)
+      s_terms[2 * kTabAxis + i] = packed_term(i, v.bz, v.plane, v.bx + v.by);
   }
   __syncthreads();
 }
@@ -205,9 +226,11 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
 };
 
 // Entry of the footprint with corner k (kx, ky in [0, n - 1]) in packed
-// plane z of a packed volume.
+// plane z of a packed volume: three LDS terms (TAB) or the index arithmetic.
+template <bool TAB>
 __device__ __forceinline__ int packed_entry(const DevVolume& v, int kx, int ky, int z) {
-  return packed_index(kx + 1, ky + 1, z, v.bx, v.by, v.bz, v.row, v.plane);
+  if constexpr (TAB) return s_terms[kx] + s_terms[kTabAxis + ky] + s_terms[2 * kTabAxis + z];
+  else return packed_index(kx + 1, ky + 1, z, v.bx, v.by, v.bz, v.row, v.plane);
 }
 
 // Four float32 texels, or eight 16-bit texels packed two to a word (low half
@@ -227,13 +250,13 @@ __device__ __forceinline__ void decode_packed(const uint32_t (&w)[N], float (&c)
 // packed_index): entry (z, y, x) holds the texels at (x, y), (x+1, y),
 // (x, y+1), (x+1, y+1) of plane z (edge-clamped), so a lookup is two aligned
 // fetches, one per z plane.
-template <int DT>
-struct BaseSampler<DT, LAYOUT_QUAD> {
+template <int DT, bool TAB>
+struct QuadSampler {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
     const int za = kz, zb = min(kz + 1, v.nz - 1);
-    const int ia = packed_entry(v, kx, ky, za), ib = packed_entry(v, kx, ky, zb);
+    const int ia = packed_entry<TAB>(v, kx, ky, za), ib = packed_entry<TAB>(v, kx, ky, zb);
     const int ea = live ? ia : 0;
     const int eb = live ? ib : 0;
     // entries are non-negative: index with 32-bit unsigned offsets
@@ -257,16 +280,21 @@ struct BaseSampler<DT, LAYOUT_QUAD> {
   }
 };
 
+template <int DT>
+struct BaseSampler<DT, LAYOUT_QUAD> : QuadSampler<DT, false> {};
+template <int DT>
+struct BaseSampler<DT, LAYOUT_QUAD | kLayoutTab> : QuadSampler<DT, true> {};
+
 // Oct layout, (nz+1) x (ny+1) x (nx+1) entries of 8 texels in bricks: entry
 // (z, y, x) holds the whole 2x2x2 footprint (the quad of plane z, then the
 // quad of plane z+1, edge-clamped), so a lookup is one aligned fetch (two for
 // float32).
-template <int DT>
-struct BaseSampler<DT, LAYOUT_OCT> {
+template <int DT, bool TAB>
+struct OctSampler {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
   __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
                                               uint32_t (&w)[kWords]) {
-    const int ie = packed_entry(v, kx, ky, kz + 1);
+    const int ie = packed_entry<TAB>(v, kx, ky, kz + 1);
     const int e = live ? ie : 0;
     if constexpr (DT == DT_F32) {
       const uint4* q = static_cast<const uint4*>(v.base) + 2 * (size_t)(uint32_t)e;
@@ -286,6 +314,11 @@ struct BaseSampler<DT, LAYOUT_OCT> {
     for (int k = 0; k < 4; ++k) p[k] = w[k];
   }
 };
+
+template <int DT>
+struct BaseSampler<DT, LAYOUT_OCT> : OctSampler<DT, false> {};
+template <int DT>
+struct BaseSampler<DT, LAYOUT_OCT | kLayoutTab> : OctSampler<DT, true> {};
 
 // Trilinear lookup of the base volume at continuous texel coordinates f.
 template <int DT, int LAYOUT>
@@ -415,7 +448,8 @@ __device__ __forceinline__ float density_tex(const DevVolume& v, float fx, float
   } else {
     if (!(b > 0.0f)) return 0.0f;
     float d;
-    if constexpr (LAYOUT == LAYOUT_DENSE) d = trilerp_repeat<DT>(v.detail, v.dnx, v.dny, v.dnz, gx, gy, gz);
+    if constexpr ((LAYOUT & 3) == LAYOUT_DENSE)
+      d = trilerp_repeat<DT>(v.detail, v.dnx, v.dny, v.dnz, gx, gy, gz);
     else d = detail_oct<DT>(v, gx, gy, gz);
     const float wd = v.detail_weight * d;
     return fminf(fmaxf((b - wd) / (1.0f - wd), 0.0f), 1.0f);

@@ -21,6 +21,12 @@ struct Tuning {
 };
 Tuning& tuning();
 
+// Layout argument of the sampling kernels for a volume: a packed layout whose
+// volume fits the LDS entry-index tables (tab_fits) carries kLayoutTab.
+inline int sampler_layout(const DevVolume& v, int layout) {
+  return layout != LAYOUT_DENSE && tab_fits(v.nx, v.ny, v.nz) ? layout | kLayoutTab : layout;
+}
+
 // Render tile walk under the current
 // tuning: super-tile side S and XCD run length L (0 = contiguous runs).
 struct TileWalk {

@@ -17,6 +17,16 @@ constexpr int kMaxViews = 16;   // cameras carried by value in one launch
 // replicate each lookup's footprint so that it is one aligned fetch.
 enum { LAYOUT_DENSE = 0, LAYOUT_QUAD = 1, LAYOUT_OCT = 2 };
 
+// A packed entry index is the sum of a term of x, a term of y and a term of
+// z (see packed_index). For a volume of at most kTabAxis texels along x and
+// y and fewer along z, the kernels stage those terms in LDS tables and index
+// through them; the sampler's layout argument then carries kLayoutTab.
+constexpr int kLayoutTab = 4;
+constexpr int kTabAxis = 1024;
+inline __host__ __device__ bool tab_fits(int nx, int ny, int nz) {
+  return nx <= kTabAxis && ny <= kTabAxis && nz < kTabAxis;
+}
+
 // Entry order of the packed layouts: bricks of 2^bx x 2^by x 2^bz entries --
 // 8 in all, one 128-byte line of 16-byte entries -- x fastest inside a brick,
 // then y, then z, with the bricks themselves row-major. The shape is a

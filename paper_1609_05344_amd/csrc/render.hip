@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
   int px, py;
   tile_pixel(tx, ty, wave, lane, px, py);
   const bool inside = px < W && py < H;
-  stage_occupancy(vol);
+  stage_volume<LAYOUT>(vol);
   if (!COUNT && !inside) return;
 
   RayResult r = {0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, 0u, 0.0f};
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void rays_kernel(DevVolume vol, DevParams prm,
                                                    const uint32_t* __restrict__ pixel_xy,
                                                    long long n, float4* __restrict__ out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  stage_occupancy(vol);
+  stage_volume<LAYOUT>(vol);
   if (i >= n) return;
   const float ox = origins[3 * i], oy = origins[3 * i + 1], oz = origins[3 * i + 2];
   float dx = dirs[3 * i], dy = dirs[3 * i + 1], dz = dirs[3 * i + 2];
@@ -232,6 +232,8 @@ static hipError_t dispatch_l(int layout, bool detail, int mode, F& f) {
   switch (layout) {
     case LAYOUT_QUAD: return dispatch_dc<F, DT, LAYOUT_QUAD>(detail, mode, f);
     case LAYOUT_OCT: return dispatch_dc<F, DT, LAYOUT_OCT>(detail, mode, f);
+    case LAYOUT_QUAD | kLayoutTab: return dispatch_dc<F, DT, LAYOUT_QUAD | kLayoutTab>(detail, mode, f);
+    case LAYOUT_OCT | kLayoutTab: return dispatch_dc<F, DT, LAYOUT_OCT | kLayoutTab>(detail, mode, f);
     default: return dispatch_dc<F, DT, LAYOUT_DENSE>(detail, mode, f);
   }
 }
@@ -369,7 +371,7 @@ hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevPar
                          float* depth, hipStream_t s) {
   RenderLaunch f{v, p, c, n_views, frame, W, H, out, counts, trace, depth, s};
   const int mode = counts != nullptr || trace != nullptr ? kCount : depth != nullptr ? kDepth : kImage;
-  return dispatch(dtype, layout, v.detail != nullptr, mode, f);
+  return dispatch(dtype, sampler_layout(v, layout), v.detail != nullptr, mode, f);
 }
 
 int render_residency(int dtype, int layout, bool detail) {
@@ -382,7 +384,7 @@ hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParam
                        uint32_t frame, const float* o, const float* d, const uint32_t* pxy,
                        long long n, float* out, hipStream_t s) {
   RaysLaunch f{v, p, frame, o, d, pxy, n, out, s};
-  return dispatch(dtype, layout, v.detail != nullptr, kImage, f);
+  return dispatch(dtype, sampler_layout(v, layout), v.detail != nullptr, kImage, f);
 }
 
 hipError_t launch_pack(const void* src, int elem_bytes, int nx, int ny, int nz, int layout,

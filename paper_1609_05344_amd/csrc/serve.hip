@@ -60,7 +60,7 @@ template <int DT, int LAYOUT, bool DETAIL>
 __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol,
                                                            unsigned int* __restrict__ counters,
                                                            const ServeTable* __restrict__ tab) {
-  stage_occupancy(vol);
+  stage_volume<LAYOUT>(vol);
   __shared__ int s_tile;
   const int total = tab->total_tiles, n_items = tab->n_items, S = tab->supertile;
   const int home = blockIdx.x & 7;
@@ -183,6 +183,8 @@ RenderFn pick_dt(int layout, bool detail) {
   switch (layout) {
     case LAYOUT_QUAD: return pick_l<DT, LAYOUT_QUAD>(detail);
     case LAYOUT_OCT: return pick_l<DT, LAYOUT_OCT>(detail);
+    case LAYOUT_QUAD | kLayoutTab: return pick_l<DT, LAYOUT_QUAD | kLayoutTab>(detail);
+    case LAYOUT_OCT | kLayoutTab: return pick_l<DT, LAYOUT_OCT | kLayoutTab>(detail);
     default: return pick_l<DT, LAYOUT_DENSE>(detail);
   }
 }
@@ -202,7 +204,7 @@ class HipExecutor : public serve::Executor {
   HipExecutor(int device, const DevVolume& v, int dtype, int layout, float blend, bool graphs,
               int queues)
       : device_(device), vol_(v), blend_(blend), graphs_(graphs), queues_(queues) {
-    fn_ = pick(dtype, layout, v.detail != nullptr);
+    fn_ = pick(dtype, sampler_layout(v, layout), v.detail != nullptr);
   }
 
   int init(std::string* msg) {

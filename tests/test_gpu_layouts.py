@@ -208,3 +208,27 @@ def test_packed_detail_matches_dense_and_oracle(cf, dtype):
         assert np.array_equal(to_np(cf.cloud_render(v, cam, w.params, 2, 64, 48)), dense)
     tol = FP32_TOL if dtype == "f32" else HALF_TOL
     assert max_err(dense, O.render(oracle_volume(sc), cam, w.params, 64, 48, frame=2)) < tol
+
+
+@pytest.mark.parametrize("dims", [(1024, 3, 1023), (1025, 3, 2), (2, 1030, 3), (3, 2, 1024)])
+def test_index_tables_and_their_limits(cf, dims):
+    # packed volumes of at most 1024 texels along x and y and fewer along z are
+    # indexed through entry-index tables in LDS, larger ones by the index
+    # arithmetic: both sides of each limit, packed against dense bitwise and
+    # against the oracle
+    nx, ny, nz = dims
+    say(f"volume {dims}: quad and oct vs dense, and vs the oracle")
+    w = scenes.workload("C1", jitter=1)
+    rng = np.random.default_rng(nx + 7 * ny + 13 * nz)
+    base = np.clip(rng.uniform(-0.3, 1.0, size=(nz, ny, nx)), 0, 1)
+    st = scenes.quantise(base, "f32")
+    sc = scenes.Scene(w, st, scenes.decode(st, "f32"))
+    cam = scenes.orbit_camera(1.6, 205.0, 30.0)
+    dense = to_np(cf.cloud_render(cf.device_volume(sc), cam, w.params, 2, 48, 40))
+    for layout in ("quad", "oct"):
+        got = to_np(cf.cloud_render(cf.device_volume(sc, layout=layout, occupancy=True), cam, w.params,
+                                    2, 48, 40))
+        assert np.array_equal(got, dense), layout
+    want = O.render(oracle_volume(sc), cam, w.params, 48, 40, frame=2)
+    assert max_err(dense, want) < FP32_TOL
+    assert want[..., 3].max() > 0.05

@@ -142,15 +142,9 @@ __device__ __forceinline__ int packed_term(int i, int sh, int stride, int low_sh
   return (mul24(i >> sh, stride) << 3) | ((i & ((1 << sh) - 1)) << low_shift);
 }
 
-// Copies the volume's occupancy bitmap (if any) into LDS and, for a
-// table-indexed packed layout, builds the entry-index terms there. Every
-// thread of the workgroup must call it before sampling (it ends with a
-// barrier).
+// Entry-index terms of a table-indexed packed layout into LDS (no barrier).
 template <int LAYOUT>
-__device__ __forceinline__ void stage_volume(const DevVolume& v) {
-  if (v.occ) {
-    for (int i = threadIdx.x; i < v.occ_words; i += blockDim.x) s_occupancy[i] = v.occ[i];
-  }
+__device__ __forceinline__ void build_terms(const DevVolume& v) {
   if constexpr ((LAYOUT & kLayoutTab) != 0) {
     // packed planes: 0..nz-1 (quad), 0..nz (oct); the host checked tab_fits
     const int planes = (LAYOUT & 3) == LAYOUT_OCT ? v.nz + 1 : v.nz;
@@ -160,6 +154,45 @@ __device__ __forceinline__ void stage_volume(const DevVolume& v) {
     for (int i = threadIdx.x; i < planes; i += blockDim.x)
       s_terms[2 * kTabAxis + i] = packed_term(i, v.bz, v.plane, v.bx + v.by);
   }
+}
+
+// Copies the volume's occupancy bitmap (if any) into LDS and, for a
+// table-indexed packed layout, builds the entry-index terms there. Every
+// thread of the workgroup must call it before sampling (it ends with a
+// barrier).
+template <int LAYOUT>
+__device__ __forceinline__ void stage_volume(const DevVolume& v) {
+  if (v.occ) {
+    for (int i = threadIdx.x; i < v.occ_words; i += blockDim.x) s_occupancy[i] = v.occ[i];
+  }
+  build_terms<LAYOUT>(v);
+  __syncthreads();
+}
+
+// The same staging in two halves, for 256-thread workgroups: the first
+// issues the bitmap loads into registers, the second stores them, builds the
+// terms and waits, so that work placed between the two (a ray's set-up)
+// overlaps the loads.
+struct StagedOccupancy {
+  uint32_t w[kOccupancyWords / 256];
+};
+__device__ __forceinline__ void stage_volume_begin(const DevVolume& v, StagedOccupancy& r) {
+#pragma unroll
+  for (int k = 0; k < kOccupancyWords / 256; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    r.w[k] = v.occ && i < v.occ_words ? v.occ[i] : 0u;
+  }
+}
+template <int LAYOUT>
+__device__ __forceinline__ void stage_volume_end(const DevVolume& v, const StagedOccupancy& r) {
+  if (v.occ) {
+#pragma unroll
+    for (int k = 0; k < kOccupancyWords / 256; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < v.occ_words) s_occupancy[i] = r.w[k];
+    }
+  }
+  build_terms<LAYOUT>(v);
   __syncthreads();
 }
 

@@ -67,18 +67,22 @@ __global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume
   int px, py;
   tile_pixel(tx, ty, wave, lane, px, py);
   const bool inside = px < W && py < H;
-  stage_volume<LAYOUT>(vol);
+  // the ray's set-up runs while the occupancy bitmap is on its way to LDS
+  StagedOccupancy staged;
+  stage_volume_begin(vol, staged);
+  const DevCamera& c = cams.c[view];
+  float dx = 0.0f, dy = 0.0f, dz = 1.0f, j = 0.5f;
+  if (inside) {
+    camera_dir(c, px, py, W, H, dx, dy, dz);
+    j = jitter_for(prm.jitter, (uint32_t)px, (uint32_t)py, frame, prm.seed);
+  }
+  stage_volume_end<LAYOUT>(vol, staged);
   if (!COUNT && !inside) return;
 
   RayResult r = {0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, 0u, 0.0f};
-  if (inside) {
-    const DevCamera& c = cams.c[view];
-    float dx, dy, dz;
-    camera_dir(c, px, py, W, H, dx, dy, dz);
-    const float j = jitter_for(prm.jitter, (uint32_t)px, (uint32_t)py, frame, prm.seed);
+  if (inside)
     r = march<DT, LAYOUT, DETAIL, COUNT, MODE == kDepth>(vol, prm, c.pos[0], c.pos[1], c.pos[2],
                                                          dx, dy, dz, j);
-  }
   if constexpr (COUNT) {
     if (counts) {
       const uint32_t s = wave_sum(r.lookups);

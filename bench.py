@@ -452,8 +452,9 @@ def quality_report(cf, scenes, torch) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed frames first: the GPU clocks settle over the first ~20 ms of load")
     ap.add_argument("--workload", default="H")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--layout", default="quad", choices=["dense", "quad", "oct"])

@@ -10,15 +10,24 @@ namespace cloud {
 // Temporal resolve (Section 3.2): a tile of 256 pixels of the current frame
 // (TW wide) plus a one-pixel edge-clamped halo is staged in LDS, so each
 // current pixel is read from HBM about once although nine threads use it.
+// Tiles are row-major. With xcd_runs, each XCD takes one contiguous eighth of
+// them (workgroups are dealt to the XCDs round-robin), so a tile's halo rows
+// were mostly just read by a neighbour in the same L2; without, consecutive
+// tiles go to different XCDs.
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int taa_tile(int xcd_runs) {
+  return xcd_runs ? xcd_walk(blockIdx.x, gridDim.x, 0) : (int)blockIdx.x;
+}
 
 template <int TW>
 __global__ __launch_bounds__(256) void taa_kernel(const float4* __restrict__ cur,
                                                   const float4* hist, float4* out, int W, int H,
-                                                  int tiles_x, float blend) {
+                                                  int tiles_x, float blend, int xcd_runs) {
   constexpr int TH = 256 / TW;
   __shared__ float4 tile[TH + 2][TW + 2];
-  const int tyi = blockIdx.x / tiles_x, txi = blockIdx.x - tyi * tiles_x;
+  const int t = taa_tile(xcd_runs);
+  const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
   const int bx = txi * TW, by = tyi * TH;
   for (int i = threadIdx.x; i < (TH + 2) * (TW + 2); i += 256) {
     const int ly = i / (TW + 2), lx = i - ly * (TW + 2);
@@ -78,10 +87,12 @@ __global__ __launch_bounds__(256) void taa_reproject_kernel(const float4* __rest
                                                             const float4* __restrict__ hist,
                                                             float4* __restrict__ out, DevCamera cam,
                                                             DevCamera prev, int W, int H,
-                                                            int tiles_x, float blend) {
+                                                            int tiles_x, float blend,
+                                                            int xcd_runs) {
   constexpr int TH = 256 / TW;
   __shared__ float4 tile[TH + 2][TW + 2];
-  const int tyi = blockIdx.x / tiles_x, txi = blockIdx.x - tyi * tiles_x;
+  const int t = taa_tile(xcd_runs);
+  const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
   const int bx = txi * TW, by = tyi * TH;
   for (int i = threadIdx.x; i < (TH + 2) * (TW + 2); i += 256) {
     const int ly = i / (TW + 2), lx = i - ly * (TW + 2);
@@ -139,6 +150,14 @@ __global__ __launch_bounds__(256) void taa_reproject_kernel(const float4* __rest
                        fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w));
 }
 
+// Contiguous XCD runs pay while the resolve's frames (current, history and
+// output: 48 bytes a pixel) stay inside the 256 MB last-level cache: measured
+// 15 % faster from 720p to 1440p, 14 % slower at 4K, where the eight XCDs'
+// separate streams then reach HBM.
+static int taa_xcd_runs(int W, int H) {
+  return 48.0 * W * H <= 192.0 * (1 << 20) ? 1 : 0;
+}
+
 hipError_t launch_taa_reproject(const float* cur, const float* depth, const float* hist,
                                 float* out, const DevCamera& cam, const DevCamera& prev, int W,
                                 int H, float blend, hipStream_t s) {
@@ -147,7 +166,7 @@ hipError_t launch_taa_reproject(const float* cur, const float* depth, const floa
   hipLaunchKernelGGL(taa_reproject_kernel<TW>, dim3(tiles_x * tiles_y), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(cur), depth,
                      reinterpret_cast<const float4*>(hist), reinterpret_cast<float4*>(out), cam,
-                     prev, W, H, tiles_x, blend);
+                     prev, W, H, tiles_x, blend, taa_xcd_runs(W, H));
   return hipGetLastError();
 }
 
@@ -166,12 +185,13 @@ hipError_t launch_taa(const float* cur, const float* hist, float* out, int W, in
   const int th = 256 / tw;
   const int tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
   const dim3 grid(tiles_x * tiles_y);
+  const int runs = taa_xcd_runs(W, H);
   if (tw == 64)
-    hipLaunchKernelGGL(taa_kernel<64>, grid, dim3(256), 0, s, c4, h4, o4, W, H, tiles_x, blend);
+    hipLaunchKernelGGL(taa_kernel<64>, grid, dim3(256), 0, s, c4, h4, o4, W, H, tiles_x, blend, runs);
   else if (tw == 32)
-    hipLaunchKernelGGL(taa_kernel<32>, grid, dim3(256), 0, s, c4, h4, o4, W, H, tiles_x, blend);
+    hipLaunchKernelGGL(taa_kernel<32>, grid, dim3(256), 0, s, c4, h4, o4, W, H, tiles_x, blend, runs);
   else
-    hipLaunchKernelGGL(taa_kernel<16>, grid, dim3(256), 0, s, c4, h4, o4, W, H, tiles_x, blend);
+    hipLaunchKernelGGL(taa_kernel<16>, grid, dim3(256), 0, s, c4, h4, o4, W, H, tiles_x, blend, runs);
   return hipGetLastError();
 }
 

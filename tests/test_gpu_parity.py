@@ -348,7 +348,9 @@ def test_c3_detail_sampled(cf, torch, dtype):
 # temporal resolve
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("W,H", [(1280, 720), (37, 23), (1, 1), (16, 1)])
+# 4096x2050 is past the size at which the resolve's tiles stop being dealt to
+# the XCDs in contiguous runs
+@pytest.mark.parametrize("W,H", [(1280, 720), (37, 23), (1, 1), (16, 1), (4096, 2050)])
 def test_taa_parity(cf, torch, W, H):
     say(f"resolve {W}x{H}")
     rng = np.random.default_rng(W * 7 + H)

@@ -63,6 +63,11 @@ def recorded_counters(config: dict) -> dict:
     return rec
 
 
+def counter_config(workload: str, dtype: str, layout: str, occupancy: bool) -> dict:
+    """The key a counter record is filed under: the render configuration."""
+    return {"workload": workload, "dtype": dtype, "layout": layout, "occupancy": occupancy}
+
+
 def recorded_traffic(config: dict):
     return recorded_counters(config).get("traffic_bytes_per_launch")
 
@@ -626,8 +631,7 @@ def main():
     elem = 4 if args.dtype == "f32" else 2
     bytes_per_lookup = 8 * elem * (2 if w.detail_n else 1)   # base (+ detail) footprint
     achieved = lk_frame * bytes_per_lookup / (render_ms * 1e-3) / 1e9
-    traffic_key = {"workload": w.name, "dtype": args.dtype, "layout": args.layout,
-                   "occupancy": not args.no_occupancy}
+    traffic_key = counter_config(w.name, args.dtype, args.layout, not args.no_occupancy)
     line = {
         "metric": "Gsamples/s @1080p 8-step+TAA (executed trilinear density lookups per second; "
                   "ms/frame in ms_per_step)",

@@ -27,6 +27,8 @@ def test_counter_record_applies_only_to_its_sources_and_config():
         assert bench.recorded_traffic(cfg) == rec["traffic_bytes_per_launch"]
     else:
         assert bench.recorded_traffic(cfg) is None
+    # filed under the key the default bench run looks up (H, FP32, quad, occupancy)
+    assert cfg == bench.counter_config("H", "f32", "quad", True)
     other = dict(cfg, dtype="bf16")
     assert bench.recorded_traffic(other) is None
     assert bench.recorded_counters(other) == {}

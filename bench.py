@@ -7,7 +7,7 @@ plus ambient, analytic step integration (one render launch), then the
 3x3-clamped temporal resolve into the history (one resolve launch). The
 camera orbits one degree per frame, as in the paper's moving-scene use.
 
-    python bench.py [--gpus 1] [--steps 60] [--warmup 10]
+    python bench.py [--gpus 1] [--steps 300] [--warmup 200]
 
 Prints one JSON line. `value` is executed trilinear density lookups per
 second (Gsamples/s) over the timed frames, inputs resident in HBM; the
@@ -17,6 +17,7 @@ per-frame lookup count comes from the library's own counter (not timed).
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import multiprocessing as mp
@@ -61,6 +62,49 @@ def recorded_counters(config: dict) -> dict:
     if rec.get("source_sha1") != kernel_source_sha1() or rec.get("config") != config:
         return {}
     return rec
+
+
+# ---------------------------------------------------------------------------
+# Timing events
+# ---------------------------------------------------------------------------
+
+_HIP = None
+
+
+class TimingEvent:
+    """A HIP timing event on torch's current stream (the stream the library
+    launches on), recorded without the system-scope fence
+    (hipEventDisableSystemFence). A default event writes back and invalidates
+    the caches when it completes, which adds about 1.7 us a record at 1080p and
+    slows the kernel after it. Read only after a device-wide synchronize."""
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self):
+        global _HIP
+        import torch
+        if _HIP is None:   # the HIP runtime torch loaded (same soname as the library's)
+            _HIP = ctypes.CDLL("libamdhip64.so.7")
+        self.h = ctypes.c_void_p()
+        self.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        self._check(_HIP.hipEventCreateWithFlags(ctypes.byref(self.h),
+                                                 ctypes.c_uint(self.DISABLE_SYSTEM_FENCE)))
+
+    @staticmethod
+    def _check(rc):
+        if rc != 0:
+            raise RuntimeError(f"HIP event call failed with error {rc}")
+
+    def record(self):
+        self._check(_HIP.hipEventRecord(self.h, self.stream))
+
+    def elapsed_time(self, end: "TimingEvent") -> float:
+        ms = ctypes.c_float()
+        self._check(_HIP.hipEventElapsedTime(ctypes.byref(ms), self.h, end.h))
+        return ms.value
+
+    def __del__(self):
+        if _HIP is not None and self.h:
+            _HIP.hipEventDestroy(self.h)
 
 
 def counter_config(workload: str, dtype: str, layout: str, occupancy: bool) -> dict:
@@ -167,7 +211,7 @@ def paper_table(cf, scenes, torch, np, dtype: str, layout: str, frames=range(10,
         n_lk = int(lk.item()) / len(frames)
         ev = []
         for f in frames:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e = [TimingEvent() for _ in range(4)]
             e[0].record()
             cf.cloud_render(vol, base.camera(f), p, f, W, H, out=cur)
             e[1].record()
@@ -217,7 +261,7 @@ def gather_ceiling(cf, torch, np, w, vol, p, frames, render_ms: float, bytes_per
         torch.cuda.synchronize()
         ev = []
         for f in frames:     # launched back to back, like the render frames
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a, b = TimingEvent(), TimingEvent()
             a.record()
             cf.cloud_gather_ceiling(vol, cams[f], p, f, W, H, traces[f], mode, out=out)
             b.record()
@@ -584,8 +628,10 @@ def main():
         DW, DH = w.display
         sky = torch.tensor(scenes.sky_background(DW, DH), device=dev)
         frame_out = torch.empty((DH, DW, 4), device=dev)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    # per timed frame: before and after the render (the next frame's first
+    # event, or `end`, closes the frame)
+    ev = [(TimingEvent(), TimingEvent()) for _ in range(args.steps)]
+    end = TimingEvent()
 
     def frame(f, events=None):
         resolve(f, events)
@@ -619,10 +665,13 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         frame(args.warmup + k, ev[k])
+    end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     render_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    starts = [a for a, _ in ev] + [end]
+    frame_ms = np.array([starts[k].elapsed_time(starts[k + 1]) for k in range(args.steps)])
     lk_timed = int(counts[args.warmup:].sum())
     lk_frame = lk_timed / args.steps
     ms_per_step = wall * 1e3 / args.steps
@@ -660,12 +709,16 @@ def main():
                      "traffic": recorded_traffic(traffic_key), "kernel": "render_kernel",
                      "valu": valu_fraction(recorded_counters(traffic_key), render_ms),
                      "kernel_ms": round(render_ms, 4),
+                     "events": "HIP events on the launch stream, hipEventDisableSystemFence",
                      "algorithmic_bytes_per_launch": round(lk_frame * bytes_per_lookup),
                      "bytes_per_lookup": bytes_per_lookup,
                      "traffic_note": "HBM bytes per launch: calibrated rocprofv3 FETCH_SIZE + "
                                      "WRITE_SIZE recorded in profiles/render_traffic.json for "
                                      "this kernel source and config (null if either changed)"},
         "cpu_baseline": cpu,
+        # HIP-event time from each timed frame's start to the next one's
+        "frame_ms": {"median": round(float(np.median(frame_ms)), 4),
+                     "p90": round(float(np.percentile(frame_ms, 90)), 4)},
     }
     if not args.no_ceiling:
         line["gather_ceiling"] = gather_ceiling(cf, torch, np, w, vol, p,

@@ -191,8 +191,9 @@ def paper_table(cf, scenes, torch, np, dtype: str, layout: str, frames=range(10,
     """Each row of the paper's timing table: the cloud render at that
     resolution and step count (H's volume and camera orbit), plus the
     resolve and the up-sample + composite into the 1920x1080 frame where the
-    row has them. HIP-event means over the frames given; lookups counted by
-    the library outside the timed launches."""
+    row has them. HIP-event means over the frames given, after ten untimed
+    frames of the row (the first launch of a kernel in a process is slow);
+    lookups counted by the library outside the timed launches."""
     from dataclasses import replace
     base = scenes.workload("H")
     vol = cf.device_volume(scenes.make_scene(base, dtype=dtype), layout=layout, occupancy=True)
@@ -209,19 +210,23 @@ def paper_table(cf, scenes, torch, np, dtype: str, layout: str, frames=range(10,
         for f in frames:
             cf.cloud_count_lookups(vol, base.camera(f), p, f, W, H, out=lk)
         n_lk = int(lk.item()) / len(frames)
-        ev = []
-        for f in frames:
-            e = [TimingEvent() for _ in range(4)]
+        def frame(f, e):
             e[0].record()
             cf.cloud_render(vol, base.camera(f), p, f, W, H, out=cur)
             e[1].record()
             if taa:
-                cf.cloud_taa_resolve(cur, hist, hist, w.taa_blend, f - frames[0])
+                cf.cloud_taa_resolve(cur, hist, hist, w.taa_blend, f)
             e[2].record()
             if (W, H) != (1920, 1080):
                 cf.cloud_composite(hist if taa else cur, sky, out=full)
             e[3].record()
-            ev.append(e)
+
+        for f in range(max(frames[0] - 10, 0), frames[0]):
+            frame(f, [TimingEvent() for _ in range(4)])
+        torch.cuda.synchronize()
+        ev = [[TimingEvent() for _ in range(4)] for _ in frames]
+        for f, e in zip(frames, ev):
+            frame(f, e)
         torch.cuda.synchronize()
         r = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
         t = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))

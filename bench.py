@@ -159,6 +159,61 @@ def cpu_baseline(name: str, dtype: str, frames: int, cores: int) -> dict:
             "ms_per_frame": round(dt * 1e3 / frames, 1)}
 
 
+_SUBSET_SCENES = {}
+
+
+def _oracle_subset_job(args):
+    name, dtype, view, steps, jitter, pix = args
+    from dataclasses import replace
+    from oracle import cloud as O
+    from paper_1609_05344_amd import scenes
+    w = scenes.workload(name)
+    if (name, dtype) not in _SUBSET_SCENES:     # one volume load per worker process
+        sc = scenes.make_scene(w, dtype=dtype)
+        _SUBSET_SCENES[(name, dtype)] = O.OracleVolume(
+            base=sc.base_f64, detail=sc.detail_f64, detail_weight=w.params.detail_weight,
+            detail_tiling=w.params.detail_tiling)
+    vol = _SUBSET_SCENES[(name, dtype)]
+    p = replace(w.params, steps=steps, jitter=jitter)
+    t = time.perf_counter()
+    _, lk = O.render(vol, w.camera(0, view=view), p, w.width, w.height, frame=0, pixels=pix,
+                     return_lookups=True)
+    return lk, time.perf_counter() - t
+
+
+def oracle_subset(name: str, dtype: str, steps: int, jitter: int, per_view: int,
+                  cores: int) -> dict:
+    """The oracle's rate on a seeded subset of per_view pixels of every view,
+    for a reference too large to render whole on the host (C5 at 128 steps is
+    about 59 G lookups a launch). Times the renders only, not volume loads."""
+    import numpy as np
+    from paper_1609_05344_amd import scenes
+    w = scenes.workload(name)
+    scenes.make_scene(w, dtype=dtype)          # generate/cache the volume once
+    chunks = max(1, 2 * cores // w.views)
+    jobs = [(name, dtype, v, steps, jitter, c)
+            for v in range(w.views)
+            for c in np.array_split(scenes.random_pixels(w.width, w.height, per_view,
+                                                         seed=4096 + v), chunks)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_subset_job, [(name, dtype, 0, 1, 0, jobs[0][5][:4])] * cores)  # load
+        t = time.perf_counter()
+        res = pool.map(_oracle_subset_job, jobs)
+        wall = time.perf_counter() - t
+    lookups = sum(r[0] for r in res)
+    n_pix = per_view * w.views
+    full_px = w.width * w.height * w.views
+    return {"metric": "oracle rate on a pixel subset", "workload": name, "dtype": dtype,
+            "steps": steps, "jitter": JITTER_NAMES[jitter], "pixels": n_pix,
+            "views": w.views, "lookups": int(lookups), "wall_s": round(wall, 2),
+            "gsamples_per_s": round(lookups / wall / 1e9, 4),
+            "ms_per_pixel": round(wall * 1e3 / n_pix, 5),
+            "projected_s_per_launch": round(wall / n_pix * full_px, 1),
+            "cores": cores, "kind": "oracle",
+            "note": "FP64 numpy over the decoded volume, processes over pixel chunks"}
+
+
 def valu_fraction(rec: dict, render_ms: float):
     """Wave-level VALU instructions per launch (SQ_INSTS_VALU) x 64 lanes over
     the render's duration, against the non-packed FP32 issue peak."""
@@ -541,6 +596,9 @@ def main():
     ap.add_argument("--quality", action="store_true",
                     help="print the precision-form and step-count error report instead")
     ap.add_argument("--cpu-frames", type=int, default=36)
+    ap.add_argument("--oracle-ref", default="",
+                    help="time the FP64 oracle's 128-step unjittered reference of this workload "
+                         "on 4096 seeded pixels per view (CPU only), one JSON line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="launch one plain copy of this many MiB first (counter calibration)")
@@ -559,6 +617,12 @@ def main():
         from paper_1609_05344_amd import scenes
         for dt, lay in (("f32", "quad"), ("f16", "oct")):
             print(json.dumps(paper_table(cf, scenes, torch, np, dt, lay)), flush=True)
+        return
+
+    if args.oracle_ref:
+        w = args.oracle_ref
+        print(json.dumps(oracle_subset(w, "f16" if w == "C5" else "f32", 128, 0, 4096,
+                                       min(os.cpu_count() or 1, 16))), flush=True)
         return
 
     if args.quality:

@@ -40,3 +40,16 @@ def test_valu_fraction():
     # 1e6 wave instructions x 64 lanes in 1 ms, against 256 x 64 x 2.4e9 lane-instr/s
     assert abs(v["frac"] - 64e9 / (256 * 64 * 2.4e9)) < 1e-4
     assert v["peak"] == round(256 * 64 * 2.4e9 / 1e12, 2)
+
+
+def test_oracle_subset_counts_the_subset_lookups():
+    from oracle import cloud as O
+    from paper_1609_05344_amd import scenes
+    r = bench.oracle_subset("C1", "f32", 128, 0, 64, 2)
+    w = scenes.workload("C1")
+    sc = scenes.make_scene(w, dtype="f32")
+    vol = O.OracleVolume(base=sc.base_f64)
+    pix = scenes.random_pixels(w.width, w.height, 64, seed=4096)
+    _, lk = O.render(vol, w.camera(0), w.params, w.width, w.height, frame=0, pixels=pix,
+                     return_lookups=True)
+    assert r["pixels"] == 64 and r["lookups"] == lk and r["steps"] == 128

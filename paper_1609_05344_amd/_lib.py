@@ -140,10 +140,15 @@ def check(rc: int) -> int:
 # ---------------------------------------------------------------------------
 
 def _ptr(t) -> int:
+    """Device address of a tensor (or a raw address, or 0 for None). The
+    library reads and writes dense row-major arrays, so a tensor must be
+    contiguous."""
     if t is None:
         return 0
     if isinstance(t, int):
         return t
+    if not t.is_contiguous():
+        raise ValueError(f"tensor of shape {tuple(t.shape)} is not contiguous")
     return t.data_ptr()
 
 
@@ -207,10 +212,25 @@ def _stream(stream) -> int:
 
 
 def _out(out, shape, device):
+    """A float32 output of the given shape: `out` when given (checked), else
+    a new tensor on `device`."""
     import torch
     if out is None:
         return torch.empty(shape, dtype=torch.float32, device=device)
+    if out.dtype != torch.float32 or tuple(out.shape) != tuple(shape):
+        raise ValueError(f"out must be float32 of shape {tuple(shape)}, "
+                         f"not {out.dtype} of shape {tuple(out.shape)}")
     return out
+
+
+def _image(t, shape, what):
+    """Check an input image (None passes: the library decides whether it may
+    be absent)."""
+    import torch
+    if t is not None and (t.dtype != torch.float32 or tuple(t.shape) != tuple(shape)):
+        raise ValueError(f"{what} must be float32 of shape {tuple(shape)}, "
+                         f"not {t.dtype} of shape {tuple(t.shape)}")
+    return t
 
 
 # ---------------------------------------------------------------------------
@@ -272,6 +292,7 @@ def cloud_render_depth(volume: Volume, camera, params, frame_index: int, width: 
     out = _out(out, (height, width, 4), volume.base.device)
     if depth is None:
         depth = torch.empty((height, width), dtype=torch.float32, device=volume.base.device)
+    _image(depth, (height, width), "depth")
     cam, prm = make_camera(camera), make_params(params)
     check(load().cloud_render_depth(ctypes.byref(volume.struct), ctypes.byref(cam),
                                     ctypes.byref(prm), int(frame_index) & 0xFFFFFFFF, int(width),
@@ -284,8 +305,10 @@ def cloud_taa_resolve_reproject(current, depth, history, out, camera, prev_camer
     """Reprojected temporal resolve into `out` (which must not alias the
     inputs); returns out."""
     H, W = int(current.shape[0]), int(current.shape[1])
-    if out is None:
-        out = _out(None, (H, W, 4), current.device)
+    _image(current, (H, W, 4), "current")
+    _image(depth, (H, W), "depth")
+    _image(history, (H, W, 4), "history")
+    out = _out(out, (H, W, 4), current.device)
     cam, prev = make_camera(camera), make_camera(prev_camera)
     check(load().cloud_taa_resolve_reproject(_ptr(current), _ptr(depth), _ptr(history), _ptr(out),
                                              ctypes.byref(cam), ctypes.byref(prev), W, H,
@@ -299,6 +322,8 @@ def cloud_composite(cloud, background, out=None, stream=None):
     composite it over the background; returns out [H, W, 4]."""
     lh, lw = int(cloud.shape[0]), int(cloud.shape[1])
     H, W = int(background.shape[0]), int(background.shape[1])
+    _image(cloud, (lh, lw, 4), "cloud")
+    _image(background, (H, W, 4), "background")
     out = _out(out, (H, W, 4), background.device)
     check(load().cloud_composite(_ptr(cloud), lw, lh, _ptr(background), _ptr(out), W, H,
                                  _stream(stream)))
@@ -411,8 +436,9 @@ def cloud_jitter_offsets(pixel_xy, frame_index: int, seed: int, out=None, stream
 
 def cloud_taa_resolve(current, history, out, blend: float, frame_index: int, stream=None):
     height, width = int(current.shape[0]), int(current.shape[1])
-    if out is None:
-        out = _out(None, (height, width, 4), current.device)
+    _image(current, (height, width, 4), "current")
+    _image(history, (height, width, 4), "history")
+    out = _out(out, (height, width, 4), current.device)
     check(load().cloud_taa_resolve(_ptr(current), _ptr(history), _ptr(out), width, height,
                                    float(blend), int(frame_index) & 0xFFFFFFFF, _stream(stream)))
     return out

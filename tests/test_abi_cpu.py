@@ -134,3 +134,32 @@ def test_tune_keys_checked(lib):
         ok(b"supertile", -1)
         ok(b"xcd_run", -1)
         ok(b"taa_tile", 32)
+
+
+def test_binding_checks_tensor_layout():
+    import pytest
+    import torch
+    from paper_1609_05344_amd import _lib
+    t = torch.zeros((4, 6, 4))
+    assert _lib._ptr(t) == t.data_ptr() and _lib._ptr(None) == 0 and _lib._ptr(64) == 64
+    with pytest.raises(ValueError, match="contiguous"):
+        _lib._ptr(t.transpose(0, 1))
+    assert _lib._out(t, (4, 6, 4), "cpu") is t
+    with pytest.raises(ValueError, match="shape"):
+        _lib._out(t, (6, 4, 4), "cpu")
+    with pytest.raises(ValueError, match="float32"):
+        _lib._out(t.to(torch.float16), (4, 6, 4), "cpu")
+    assert _lib._out(None, (2, 3, 4), "cpu").shape == (2, 3, 4)
+
+
+def test_binding_checks_images():
+    import pytest
+    import torch
+    from paper_1609_05344_amd import _lib
+    cur = torch.zeros((4, 6, 4))
+    with pytest.raises(ValueError, match="history"):
+        _lib.cloud_taa_resolve(cur, torch.zeros((6, 4, 4)), None, 0.1, 1)
+    with pytest.raises(ValueError, match="current"):
+        _lib.cloud_taa_resolve(cur.double(), None, None, 0.1, 0)
+    with pytest.raises(ValueError, match="background"):
+        _lib.cloud_composite(cur, torch.zeros((8, 12, 3)))

@@ -261,7 +261,13 @@ def cloud_render_views(volume: Volume, cameras, params, frame_index: int, width:
 
 def cloud_march_rays(volume: Volume, origins, dirs, pixel_xy, params, frame_index: int = 0,
                      out=None, stream=None):
+    import torch
     n = int(origins.shape[0])
+    _image(origins, (n, 3), "origins")
+    _image(dirs, (n, 3), "dirs")
+    if pixel_xy is not None and (pixel_xy.dtype not in (torch.int32, torch.uint32)
+                                 or tuple(pixel_xy.shape) != (n, 2)):
+        raise ValueError(f"pixel_xy must be 32-bit integers of shape ({n}, 2)")
     out = _out(out, (n, 4), volume.base.device)
     prm = make_params(params)
     check(load().cloud_march_rays(ctypes.byref(volume.struct), _ptr(origins), _ptr(dirs),

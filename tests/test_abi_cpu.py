@@ -163,3 +163,14 @@ def test_binding_checks_images():
         _lib.cloud_taa_resolve(cur.double(), None, None, 0.1, 0)
     with pytest.raises(ValueError, match="background"):
         _lib.cloud_composite(cur, torch.zeros((8, 12, 3)))
+
+
+def test_binding_checks_rays():
+    import pytest
+    import torch
+    from paper_1609_05344_amd import _lib
+    o = torch.zeros((2, 3))
+    with pytest.raises(ValueError, match="dirs"):
+        _lib.cloud_march_rays(None, o, torch.zeros((2, 2)), None, None)
+    with pytest.raises(ValueError, match="pixel_xy"):
+        _lib.cloud_march_rays(None, o, o, torch.zeros((2, 2)), None)

@@ -434,8 +434,10 @@ int cloud_serve_submit(cloud_server* server, uint64_t stream_id,
                        int32_t width, int32_t height, uint32_t frame_index,
                        float* out_rgba, uint64_t* request_id);
 
-/* Moves up to max finished requests into out (host array); *n_out gets the
- * count. Never blocks. */
+/* Moves up to max finished requests into out (host array of at least max
+ * entries); *n_out gets the count. Never blocks, and allocates nothing that
+ * grows with max (completions move through a fixed 64-entry buffer), so any
+ * max, however large, returns a code. */
 int cloud_serve_poll(cloud_server* server, cloud_completion* out, int32_t max,
                      int32_t* n_out);
 

@@ -2,6 +2,7 @@
 // behind the scheduler, and the cloud_serve_* C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -447,63 +448,103 @@ int cloud_serve_submit(cloud_server* srv, uint64_t stream_id, const cloud_camera
 }
 
 int cloud_serve_poll(cloud_server* srv, cloud_completion* out, int32_t max, int32_t* n_out) {
-  clear_error();
-  if (!srv || !n_out || (max > 0 && !out)) return fail(CLOUD_E_INVALID, "NULL argument");
-  std::vector<serve::Completion> tmp(max > 0 ? max : 0);
-  int n = 0;
-  srv->sched->poll(tmp.data(), max, &n);
-  for (int i = 0; i < n; ++i) {
-    out[i].request_id = tmp[i].request_id;
-    out[i].stream_id = tmp[i].stream_id;
-    out[i].status = tmp[i].status;
-    out[i].reserved = 0;
-    out[i].t_submit_ns = tmp[i].t_submit;
-    out[i].t_admit_ns = tmp[i].t_admit;
-    out[i].t_start_ns = tmp[i].t_start;
-    out[i].t_done_ns = tmp[i].t_done;
+  try {
+    clear_error();
+    if (!srv || !n_out || (max > 0 && !out)) return fail(CLOUD_E_INVALID, "NULL argument");
+    *n_out = 0;
+    // completions move out in chunks through a fixed buffer, so max bounds
+    // nothing the library allocates
+    constexpr int kChunk = 64;
+    serve::Completion tmp[kChunk];
+    int total = 0;
+    while (total < max) {
+      int n = 0;
+      srv->sched->poll(tmp, std::min(kChunk, max - total), &n);
+      for (int i = 0; i < n; ++i) {
+        cloud_completion& c = out[total + i];
+        c.request_id = tmp[i].request_id;
+        c.stream_id = tmp[i].stream_id;
+        c.status = tmp[i].status;
+        c.reserved = 0;
+        c.t_submit_ns = tmp[i].t_submit;
+        c.t_admit_ns = tmp[i].t_admit;
+        c.t_start_ns = tmp[i].t_start;
+        c.t_done_ns = tmp[i].t_done;
+      }
+      total += n;
+      *n_out = total;
+      if (n < kChunk) break;
+    }
+    return CLOUD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(CLOUD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(CLOUD_E_INVALID, "internal error");
   }
-  *n_out = n;
-  return CLOUD_OK;
 }
 
 int cloud_serve_wait(cloud_server* srv, int64_t timeout_ns) {
-  clear_error();
-  if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
-  return srv->sched->wait(timeout_ns);
+  try {
+    clear_error();
+    if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
+    return srv->sched->wait(timeout_ns);
+  } catch (const std::bad_alloc&) {
+    return fail(CLOUD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(CLOUD_E_INVALID, "internal error");
+  }
 }
 
 int cloud_serve_stats(cloud_server* srv, cloud_serve_stats_t* out) {
-  clear_error();
-  if (!srv || !out) return fail(CLOUD_E_INVALID, "NULL argument");
-  const serve::Stats s = srv->sched->stats();
-  out->queued = s.queued;
-  out->admitted = s.admitted;
-  out->running = s.running;
-  out->completed = s.completed;
-  out->rejected = s.rejected;
-  out->cancelled = s.cancelled;
-  out->failed = s.failed;
-  out->streams = s.streams;
-  out->bytes_in_use = s.bytes_in_use;
-  out->batches = s.batches;
-  return CLOUD_OK;
+  try {
+    clear_error();
+    if (!srv || !out) return fail(CLOUD_E_INVALID, "NULL argument");
+    const serve::Stats s = srv->sched->stats();
+    out->queued = s.queued;
+    out->admitted = s.admitted;
+    out->running = s.running;
+    out->completed = s.completed;
+    out->rejected = s.rejected;
+    out->cancelled = s.cancelled;
+    out->failed = s.failed;
+    out->streams = s.streams;
+    out->bytes_in_use = s.bytes_in_use;
+    out->batches = s.batches;
+    return CLOUD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(CLOUD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(CLOUD_E_INVALID, "internal error");
+  }
 }
 
 int cloud_serve_close_stream(cloud_server* srv, uint64_t stream_id) {
-  clear_error();
-  if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
-  const int rc = srv->sched->close_stream(stream_id);
-  if (rc) return fail(rc, "unknown stream");
-  return CLOUD_OK;
+  try {
+    clear_error();
+    if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
+    const int rc = srv->sched->close_stream(stream_id);
+    if (rc) return fail(rc, "unknown stream");
+    return CLOUD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(CLOUD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(CLOUD_E_INVALID, "internal error");
+  }
 }
 
 int cloud_serve_destroy(cloud_server* srv) {
-  clear_error();
-  if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
-  srv->sched.reset();   // cancels queued requests, waits for in-flight batches
-  srv->ex.reset();
-  delete srv;
-  return CLOUD_OK;
+  try {
+    clear_error();
+    if (!srv) return fail(CLOUD_E_INVALID, "server is NULL");
+    srv->sched.reset();   // cancels queued requests, waits for in-flight batches
+    srv->ex.reset();
+    delete srv;
+    return CLOUD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(CLOUD_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(CLOUD_E_INVALID, "internal error");
+  }
 }
 
 }  // extern "C"

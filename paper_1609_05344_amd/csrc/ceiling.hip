@@ -20,9 +20,6 @@ __device__ __forceinline__ uint32_t raw_lookup(const DevVolume& v, float fx, flo
   split_coord(fy, v.ny, wy, ky);
   split_coord(fz, v.nz, wz, kz);
   const bool live = OCC ? occupied(v, kx, ky, kz) : true;
-#if !CLOUD_OCC_SELECT
-  if (!live) return 0u;
-#endif
   uint32_t w[S::kWords];
   S::load(v, kx, ky, kz, live, w);
   uint32_t x = 0;

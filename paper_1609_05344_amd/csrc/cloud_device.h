@@ -14,40 +14,8 @@ namespace cloud {
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 
-#ifndef CLOUD_LIGHT_UNROLL
-#define CLOUD_LIGHT_UNROLL 6
-#endif
 // Light-march lookups issued back to back (independent loads in flight).
-constexpr int kLightUnroll = CLOUD_LIGHT_UNROLL;
-#ifndef CLOUD_PREFETCH
-#define CLOUD_PREFETCH 0
-#endif
-// A lookup in an empty brick is exactly zero. Either it branches around the
-// fetch (CLOUD_OCC_SELECT 0), or it keeps the fetch in line but points it at
-// entry 0 -- a line every wave shares, so it costs no volume traffic -- and
-// selects 0 (CLOUD_OCC_SELECT 1), which keeps the light march's fetches in
-// flight together.
-#ifndef CLOUD_OCC_SELECT
-#define CLOUD_OCC_SELECT 1
-#endif
-// 16-bit volumes: the four x-lerps of a lookup as 16-bit dot products
-// accumulated in float32, a + w (b - a) = dot((a, b), (-w, w)) + a with w
-// rounded to the storage type (1), or every lerp in float32 after decoding
-// (0). CLOUD_HALF_DOT covers FP16 (on by default: it saves the half-to-float
-// conversions), CLOUD_BF16_DOT BF16 (off: BF16 decodes with a shift, so the
-// dot products save nothing while the 8-bit weight costs accuracy).
-#ifndef CLOUD_HALF_DOT
-#define CLOUD_HALF_DOT 1
-#endif
-#ifndef CLOUD_BF16_DOT
-#define CLOUD_BF16_DOT 0
-#endif
-#if CLOUD_OCC_SELECT
-#define CLOUD_SKIP_DEAD(live) ((void)0)
-#else
-#define CLOUD_SKIP_DEAD(live) \
-  if (!(live)) return 0.0f
-#endif
+constexpr int kLightUnroll = 6;
 
 // PCG-RXS-M-XS 32-bit hash (Jarzynski and Olano, JCGT 2020).
 __device__ __forceinline__ uint32_t pcg(uint32_t v) {
@@ -86,7 +54,6 @@ __device__ __forceinline__ float jitter_for(int m, uint32_t px, uint32_t py, uin
 // ---------------------------------------------------------------------------
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
 
 template <int DT>
 __device__ __forceinline__ float texel(const void* __restrict__ base, int idx) {
@@ -363,26 +330,19 @@ __device__ __forceinline__ float base_lookup(const DevVolume& v, float fx, float
   split_coord(fy, v.ny, wy, ky);
   split_coord(fz, v.nz, wz, kz);
   const bool live = occupied(v, kx, ky, kz);
-  CLOUD_SKIP_DEAD(live);
   uint32_t w[S::kWords];
   S::load(v, kx, ky, kz, live, w);
-  if constexpr ((DT == DT_F16 && CLOUD_HALF_DOT) || (DT == DT_BF16 && CLOUD_BF16_DOT)) {
+  if constexpr (DT == DT_F16) {
+    // the four x-lerps as 16-bit dot products accumulated in float32:
+    // a + w (b - a) = dot((a, b), (-w, w)) + a, with w rounded to half
     uint32_t p[4];
     S::pairs(w, p);
     float c[4];
-    if constexpr (DT == DT_F16) {
-      const half2_t wt = {(_Float16)(-wx), (_Float16)wx};
+    const half2_t wt = {(_Float16)(-wx), (_Float16)wx};
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const half2_t h = __builtin_bit_cast(half2_t, p[k]);
-        c[k] = __builtin_amdgcn_fdot2(h, wt, (float)h.x, false);
-      }
-    } else {
-      const bf162_t wt = {(__bf16)(-wx), (__bf16)wx};
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        c[k] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf162_t, p[k]), wt,
-                                               __uint_as_float(p[k] << 16), false);
+    for (int k = 0; k < 4; ++k) {
+      const half2_t h = __builtin_bit_cast(half2_t, p[k]);
+      c[k] = __builtin_amdgcn_fdot2(h, wt, (float)h.x, false);
     }
     const float c0 = lerp(c[0], c[1], wy), c1 = lerp(c[2], c[3], wy);
     return live ? lerp(c0, c1, wz) : 0.0f;
@@ -614,28 +574,10 @@ __device__ __forceinline__ RayResult march(const DevVolume& v, const DevParams& 
   float T = 1.0f, Sr = 0.0f, Sg = 0.0f, Sb = 0.0f;
   float td = 0.0f;   // sum of (opacity added) x (sample distance), for DEPTH
   uint32_t n = 0, prim = 0, mask = 0;
-#if CLOUD_PREFETCH
-  // The next sample's density is fetched before this sample's light march,
-  // so its latency overlaps the light lookups (results are unchanged; a
-  // fetch past an early exit is simply not used).
-  float rho_next;
-  {
-    const float t0 = fmaf(j, D, tn);
-    rho_next = density<DT, LAYOUT, DETAIL>(v, fmaf(t0, dx, ox), fmaf(t0, dy, oy), fmaf(t0, dz, oz));
-  }
-#endif
   for (int i = 0; i < P.steps; ++i) {
     const float t = fmaf((float)i + j, D, tn);
     const float px = fmaf(t, dx, ox), py = fmaf(t, dy, oy), pz = fmaf(t, dz, oz);
-#if CLOUD_PREFETCH
-    const float rho = rho_next;
-    if (i + 1 < P.steps) {
-      const float t1 = fmaf((float)(i + 1) + j, D, tn);
-      rho_next = density<DT, LAYOUT, DETAIL>(v, fmaf(t1, dx, ox), fmaf(t1, dy, oy), fmaf(t1, dz, oz));
-    }
-#else
     const float rho = density<DT, LAYOUT, DETAIL>(v, px, py, pz);
-#endif
     if constexpr (COUNT) {
       n += 1;
       prim += 1;
@@ -696,16 +638,11 @@ __device__ __forceinline__ void camera_dir(const DevCamera& c, int px, int py, i
 }
 
 // Pixel of a lane in a 16x16 render tile (tx, ty): the four wavefronts of
-// the workgroup each cover a CLOUD_WAVE_W x (64 / CLOUD_WAVE_W) patch (8x8 by
-// default), so the 64 rays of a wavefront are a compact bundle.
-#ifndef CLOUD_WAVE_W
-#define CLOUD_WAVE_W 8
-#endif
+// the workgroup each cover an 8x8 patch, so the 64 rays of a wavefront are a
+// compact bundle.
 __device__ __forceinline__ void tile_pixel(int tx, int ty, int wave, int lane, int& px, int& py) {
-  constexpr int WW = CLOUD_WAVE_W, WH = 64 / WW, PER_ROW = 16 / WW;
-  static_assert(WW == 4 || WW == 8 || WW == 16, "wave patch width");
-  px = tx * 16 + (wave % PER_ROW) * WW + lane % WW;
-  py = ty * 16 + (wave / PER_ROW) * WH + lane / WW;
+  px = tx * 16 + (wave & 1) * 8 + (lane & 7);
+  py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
 }
 
 // Block index b of nb -> position in the tile walk. Workgroups are dealt to

@@ -36,21 +36,10 @@ TileWalk tile_walk() {
 // stores the image and each pixel's representative depth (into depth).
 // ---------------------------------------------------------------------------
 
-// Minimum waves per SIMD the register allocator must leave room for (0: the
-// compiler's choice).
-#ifndef CLOUD_RENDER_WAVES
-#define CLOUD_RENDER_WAVES 0
-#endif
-#if CLOUD_RENDER_WAVES > 0
-#define CLOUD_RENDER_ATTR __attribute__((amdgpu_waves_per_eu(CLOUD_RENDER_WAVES)))
-#else
-#define CLOUD_RENDER_ATTR
-#endif
-
 enum { kImage = 0, kCount = 1, kDepth = 2 };
 
 template <int DT, int LAYOUT, bool DETAIL, int MODE>
-__global__ __launch_bounds__(256) CLOUD_RENDER_ATTR void render_kernel(DevVolume vol, DevParams prm,
+__global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams prm,
                                                      DevCameras cams, uint32_t frame, int W,
                                                      int H, int tiles_x, int tiles_y, int S,
                                                      int L, float4* __restrict__ out,

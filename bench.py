@@ -33,6 +33,15 @@ MI355X_HBM_GBPS = 8000.0
 MI355X_VALU_LANE_INSTR_PER_S = 256 * 64 * 2.4e9
 MI355X_FP32_VECTOR_TFLOPS = 157.3
 KERNEL_SOURCES = ["cloud_device.h", "cloud_types.h", "render.hip"]
+# Timed frames: orbit frames TIMED_FIRST .. TIMED_FIRST + TIMED_PERIOD - 1,
+# cycled, so that the work per timed frame does not depend on --warmup or on
+# --steps (for a multiple of TIMED_PERIOD).
+TIMED_FIRST = 400
+TIMED_PERIOD = 20
+# Arithmetic type of the path for each storage type: every optical depth,
+# transmittance, exponential and colour is float32; 16-bit storage adds
+# 16-bit texels (and, for FP16, 16-bit x-lerp weights in dot products).
+PATH_DTYPE = {"f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
 
 
@@ -107,13 +116,31 @@ class TimingEvent:
             _HIP.hipEventDestroy(self.h)
 
 
+def timed_frames(steps: int) -> list:
+    """Orbit frames of the timed steps: the fixed window, cycled."""
+    return [TIMED_FIRST + k % TIMED_PERIOD for k in range(steps)]
+
+
+def warm_frames(warmup: int) -> list:
+    """The warmup frames just before the timed window (cycling below it when
+    there are more of them than frames before it)."""
+    return [TIMED_FIRST - 1 - ((warmup - 1 - k) % TIMED_FIRST) for k in range(warmup)]
+
+
+def volume_description(w, dtype: str, layout: str) -> str:
+    """What the synthetic input of workload w is, in words."""
+    v = w.volume
+    s = (f"synthetic: seeded {v.octaves}-octave value-noise FBM density {v.n}^3, coverage "
+         f"{v.coverage}" + (", slab height profile" if v.height_falloff else ""))
+    if w.detail_n:
+        s += f", eroded by a {w.detail_n}^3 Worley/value detail volume"
+    views = f", {w.views} views" if w.views > 1 else ""
+    return s + f"; {dtype} storage, {layout} layout; orbiting camera{views}"
+
+
 def counter_config(workload: str, dtype: str, layout: str, occupancy: bool) -> dict:
     """The key a counter record is filed under: the render configuration."""
     return {"workload": workload, "dtype": dtype, "layout": layout, "occupancy": occupancy}
-
-
-def recorded_traffic(config: dict):
-    return recorded_counters(config).get("traffic_bytes_per_launch")
 
 
 # ---------------------------------------------------------------------------
@@ -214,17 +241,79 @@ def oracle_subset(name: str, dtype: str, steps: int, jitter: int, per_view: int,
             "note": "FP64 numpy over the decoded volume, processes over pixel chunks"}
 
 
-def valu_fraction(rec: dict, render_ms: float):
-    """Wave-level VALU instructions per launch (SQ_INSTS_VALU) x 64 lanes over
-    the render's duration, against the non-packed FP32 issue peak."""
-    n = rec.get("valu_insts_per_launch")
-    if not n:
+# VALU lane operations the method itself needs (a minimal implementation's
+# instruction slots; the op-by-op listing is in the design notes): per
+# executed trilinear lookup of the base volume, per primary sample taken, per
+# sample that runs the light march, per pixel, and per pixel whose ray hits
+# the volume's box.
+OPS_PER_LOOKUP = 35
+OPS_PER_PRIMARY = 20
+OPS_PER_LIT = 22
+OPS_PER_PIXEL = 68
+OPS_PER_HIT = 8
+
+
+def algorithmic_ops(cf, torch, np, w, vol, p, frames) -> dict:
+    """Units of work per frame (mean over the frames): executed lookups,
+    primary samples, lit samples, pixels and hit pixels, from the library's
+    lookup trace (outside the timed launches), and the lane operations they
+    need."""
+    if p.steps > 32 or w.detail_n:
         return None
-    rate = n * 64 / (render_ms * 1e-3)
-    return {"lane_instr_per_s": round(rate / 1e12, 3), "unit": "T lane-instr/s",
-            "peak": round(MI355X_VALU_LANE_INSTR_PER_S / 1e12, 2),
-            "frac": round(rate / MI355X_VALU_LANE_INSTR_PER_S, 4),
-            "insts_per_launch": n}
+    V, W, H = w.views, w.width, w.height
+    prim = lit = hit = 0
+    for f in frames:
+        tr = cf.cloud_lookup_trace(vol, [w.camera(f, view=v) for v in range(V)], p, f, W, H)
+        t = tr.cpu().numpy().view(np.uint32).reshape(-1, 2)
+        prim += int(t[:, 0].astype(np.int64).sum())
+        m = t[:, 1].astype(np.uint64)
+        lit += int(sum(((m >> np.uint64(k)) & np.uint64(1)).sum() for k in range(32)))
+        hit += int((t[:, 0] > 0).sum())
+    n = len(frames)
+    units = {"lookups": (prim + p.light_steps * lit) / n, "primary_samples": prim / n,
+             "lit_samples": lit / n, "pixels": V * W * H, "hit_pixels": hit / n}
+    ops = (OPS_PER_LOOKUP * units["lookups"] + OPS_PER_PRIMARY * units["primary_samples"]
+           + OPS_PER_LIT * units["lit_samples"] + OPS_PER_PIXEL * units["pixels"]
+           + OPS_PER_HIT * units["hit_pixels"])
+    return {"units_per_launch": {k: round(v) for k, v in units.items()},
+            "ops_per_unit": {"lookup": OPS_PER_LOOKUP, "primary_sample": OPS_PER_PRIMARY,
+                             "lit_sample": OPS_PER_LIT, "pixel": OPS_PER_PIXEL,
+                             "hit_pixel": OPS_PER_HIT},
+            "ops_per_launch": round(ops)}
+
+
+def roofline(rec: dict, alg: dict, render_ms: float, lk_frame: float, bytes_per_lookup: int):
+    """The render kernel against the VALU issue peak (the bound: every lookup
+    is an 8-texel gather plus about 35 lane operations, and the issue slots
+    run about 80 % busy), with the HBM and issued-VALU figures measured by
+    rocprofv3 beside it."""
+    sec = render_ms * 1e-3
+    line = {"bound": "alu", "kernel": "render_kernel", "kernel_ms": round(render_ms, 4),
+            "unit": "TOP/s", "peak": round(MI355X_VALU_LANE_INSTR_PER_S / 1e12, 2),
+            "peak_note": "VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz "
+                         "(one FP32 op per lane per cycle; packed FP32 is not used)",
+            "events": "HIP events on the launch stream, hipEventDisableSystemFence"}
+    if alg:
+        a = alg["ops_per_launch"] / sec / 1e12
+        line.update({"achieved": round(a, 3), "frac": round(a / line["peak"], 4), **alg})
+    else:
+        line.update({"achieved": None, "frac": None,
+                     "note": "no lane-operation count for detail volumes or > 32 steps"})
+    traffic = rec.get("traffic_bytes_per_launch")
+    line["traffic"] = traffic
+    line["hbm"] = None if not traffic else {
+        "bytes_per_launch": traffic, "GBps": round(traffic / sec / 1e9, 1),
+        "peak_GBps": MI355X_HBM_GBPS, "frac": round(traffic / sec / 1e9 / MI355X_HBM_GBPS, 4),
+        "source": "calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE (profiles/render_traffic.json)"}
+    n = rec.get("valu_insts_per_launch")
+    line["valu_issued"] = None if not n else {
+        "wave_insts_per_launch": n,
+        "frac": round(n * 64 / sec / MI355X_VALU_LANE_INSTR_PER_S, 4),
+        "source": "rocprofv3 SQ_INSTS_VALU x 64 lanes (profiles/render_traffic.json)"}
+    line["cache_gathers"] = {"bytes_per_launch": round(lk_frame * bytes_per_lookup),
+                             "bytes_per_lookup": bytes_per_lookup,
+                             "GBps": round(lk_frame * bytes_per_lookup / sec / 1e9, 1)}
+    return line
 
 
 # ---------------------------------------------------------------------------
@@ -298,44 +387,65 @@ def paper_table(cf, scenes, torch, np, dtype: str, layout: str, frames=range(10,
 
 
 # ---------------------------------------------------------------------------
-# Gather ceiling: the render's own fetches with the arithmetic removed
+# Offset replay: the render's own fetches from precomputed corners
 # ---------------------------------------------------------------------------
 
-def gather_ceiling(cf, torch, np, w, vol, p, frames, render_ms: float, bytes_per_frame: float):
-    """Times cloud_gather_ceiling on the frames given: mode 0 replays exactly
-    the render's fetches (recorded by cloud_lookup_trace, outside the timed
-    launches), mode 1 makes as many lookups at uniformly random points of the
-    volume. The render's gather rate over mode 0's is the fraction of the
-    achievable rate for this access pattern."""
+def offset_replay(cf, torch, np, w, vol, p, frames):
+    """Times cloud_gather_replay on the given frames' recorded lookups (corner
+    codes written by cloud_gather_record outside the timed launches): mode 0
+    fetches the render's footprints in its per-wavefront order with none of
+    its arithmetic, at each residency cap, mode 1 as many uniformly random
+    footprints. Reported beside the render's own time on the same frames."""
     if p.steps > 32 or w.detail_n:
         return None
     V, W, H = w.views, w.width, w.height
     frames = list(frames)
-    cams = {f: [w.camera(f, view=v) for v in range(V)] for f in frames}
-    traces = {f: cf.cloud_lookup_trace(vol, cams[f], p, f, W, H) for f in frames}
-    out = torch.empty((V, H, W, 4), device="cuda")
-    ms = {}
-    for mode in (0, 1):
-        cf.cloud_gather_ceiling(vol, cams[frames[0]], p, frames[0], W, H, traces[frames[0]], mode,
-                                out=out)
+    recs = []
+    for f in frames:
+        cams = [w.camera(f, view=v) for v in range(V)]
+        tr = cf.cloud_lookup_trace(vol, cams, p, f, W, H)
+        recs.append(cf.cloud_gather_record(vol, cams, p, f, W, H, tr))
+        del tr
+    out = torch.empty((cf.gather_waves(V, W, H), 64), dtype=torch.int32, device="cuda")
+
+    def timed(mode, bpc, reps):
+        for codes, cnt in recs[:2]:
+            cf.cloud_gather_replay(vol, V, W, H, codes, cnt, mode=mode, blocks_per_cu=bpc, out=out)
         torch.cuda.synchronize()
         ev = []
-        for f in frames:     # launched back to back, like the render frames
+        for r in range(reps):
+            codes, cnt = recs[r % len(recs)]
             a, b = TimingEvent(), TimingEvent()
             a.record()
-            cf.cloud_gather_ceiling(vol, cams[f], p, f, W, H, traces[f], mode, out=out)
+            cf.cloud_gather_replay(vol, V, W, H, codes, cnt, mode=mode, blocks_per_cu=bpc, out=out)
             b.record()
             ev.append((a, b))
         torch.cuda.synchronize()
-        ms[mode] = [a.elapsed_time(b) for a, b in ev]
-    same, rand = float(np.mean(ms[0])), float(np.mean(ms[1]))
-    del traces
-    return {"kernel": "gather_ceiling_kernel", "frames": len(ms[0]),
-            "same_positions_ms": round(same, 4), "random_positions_ms": round(rand, 4),
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    by_cap = {bpc: timed(0, bpc, 3 * len(recs)) for bpc in (0, 2, 3, 4, 6)}
+    best = min(by_cap, key=by_cap.get)
+    rand = timed(1, best, len(recs))
+    del recs
+    img = torch.empty((V, H, W, 4), device="cuda")
+    ev = []
+    for r in range(3 * len(frames) + 2):
+        f = frames[r % len(frames)]
+        a, b = TimingEvent(), TimingEvent()
+        a.record()
+        cf.cloud_render_views(vol, [w.camera(f, view=v) for v in range(V)], p, f, W, H, out=img)
+        b.record()
+        ev.append((a, b))
+    torch.cuda.synchronize()
+    render_ms = float(np.median([a.elapsed_time(b) for a, b in ev[2:]]))
+    del img
+    return {"kernel": "gather_replay_kernel", "frames": len(frames),
+            "replay_ms_by_blocks_per_cu": {str(k): round(v, 4) for k, v in by_cap.items()},
+            "replay_ms": round(by_cap[best], 4), "random_ms": round(rand, 4),
             "render_ms": round(render_ms, 4),
-            "ceiling_GBps": round(bytes_per_frame / (same * 1e-3) / 1e9, 1),
-            "random_GBps": round(bytes_per_frame / (rand * 1e-3) / 1e9, 1),
-            "frac_of_ceiling": round(same / render_ms, 4)}
+            "render_over_replay": round(render_ms / by_cap[best], 4),
+            "note": "the replay reads 4 B of recorded corner per lane and lookup instead of "
+                    "computing it; it is not a ceiling: the render issues the same fetches faster"}
 
 
 # ---------------------------------------------------------------------------
@@ -582,8 +692,8 @@ def main():
     ap.add_argument("--jitter-mode", type=int, default=None, choices=[0, 1, 2, 3],
                     help="start offsets: 0 none, 1 per pixel (the workload's), 2 per 8x8 tile, "
                          "3 per frame")
-    ap.add_argument("--no-ceiling", action="store_true",
-                    help="skip the gather-ceiling measurement")
+    ap.add_argument("--no-replay", action="store_true",
+                    help="skip the offset-replay measurement")
     ap.add_argument("--serve-queues", type=int, default=1, choices=[1, 2])
     ap.add_argument("--serve-graphs", type=int, default=1, choices=[0, 1],
                     help="served leg: 1 replays captured graphs, 0 launches kernels one by one")
@@ -667,7 +777,6 @@ def main():
     if args.jitter_mode is not None:
         from dataclasses import replace
         p = replace(p, jitter=args.jitter_mode)
-    total = args.warmup + args.steps
 
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib * (1 << 20) // 4
@@ -677,11 +786,17 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    # executed lookups per frame (library counter, outside the timed region)
-    counts = torch.zeros((total,), dtype=torch.int64, device=dev)
-    for f in range(total):
+    # The timed window is fixed whatever --warmup is: timed step k renders
+    # orbit frame TIMED_FIRST + (k mod TIMED_PERIOD), and the warm-up frames
+    # are the ones just before it. Executed lookups per frame come from the
+    # library's counter, outside the timed region.
+    timed = timed_frames(args.steps)
+    warm = warm_frames(args.warmup)
+    counts = torch.zeros((TIMED_PERIOD,), dtype=torch.int64, device=dev)
+    for k in range(TIMED_PERIOD):
         for v in range(w.views):
-            cf.cloud_count_lookups(vol, w.camera(f, view=v), p, f, W, H, out=counts[f:f + 1])
+            cf.cloud_count_lookups(vol, w.camera(TIMED_FIRST + k, view=v), p, TIMED_FIRST + k, W, H,
+                                   out=counts[k:k + 1])
     counts = counts.cpu().numpy()
 
     V = w.views
@@ -728,12 +843,12 @@ def main():
         for v in range(V):
             cf.cloud_taa_resolve(cur[v], hist[v], hist[v], w.taa_blend, f)
 
-    for f in range(args.warmup):
+    for f in warm:
         frame(f)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        frame(args.warmup + k, ev[k])
+    for k, f in enumerate(timed):
+        frame(f, ev[k])
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -741,14 +856,14 @@ def main():
     render_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     starts = [a for a, _ in ev] + [end]
     frame_ms = np.array([starts[k].elapsed_time(starts[k + 1]) for k in range(args.steps)])
-    lk_timed = int(counts[args.warmup:].sum())
+    lk_timed = int(sum(counts[k % TIMED_PERIOD] for k in range(args.steps)))
     lk_frame = lk_timed / args.steps
     ms_per_step = wall * 1e3 / args.steps
     value = lk_timed / wall / 1e9
 
     elem = 4 if args.dtype == "f32" else 2
     bytes_per_lookup = 8 * elem * (2 if w.detail_n else 1)   # base (+ detail) footprint
-    achieved = lk_frame * bytes_per_lookup / (render_ms * 1e-3) / 1e9
+    alg = algorithmic_ops(cf, torch, np, w, vol, p, range(TIMED_FIRST, TIMED_FIRST + TIMED_PERIOD))
     traffic_key = counter_config(w.name, args.dtype, args.layout, not args.no_occupancy)
     line = {
         "metric": "Gsamples/s @1080p 8-step+TAA (executed trilinear density lookups per second; "
@@ -762,9 +877,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic: seeded 5-octave value-noise FBM density 256^3 "
-                f"({args.dtype} storage, {args.layout} layout), orbiting camera",
+        "dtype": PATH_DTYPE[args.dtype],
+        "data": volume_description(w, args.dtype, args.layout),
         "config": {"workload": f"{w.name}: {w.description}", "width": W, "height": H,
                    "display": list(w.display) or None,
                    "primary_steps": p.steps, "light_steps": p.light_steps, "jitter": JITTER_NAMES[p.jitter],
@@ -773,26 +887,16 @@ def main():
                    "occupancy_skip": not args.no_occupancy,
                    "lookups_per_frame": round(lk_frame),
                    "nominal_lookups_per_frame": V * W * H * p.steps * (1 + p.light_steps)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": MI355X_HBM_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / MI355X_HBM_GBPS, 4),
-                     "traffic": recorded_traffic(traffic_key), "kernel": "render_kernel",
-                     "valu": valu_fraction(recorded_counters(traffic_key), render_ms),
-                     "kernel_ms": round(render_ms, 4),
-                     "events": "HIP events on the launch stream, hipEventDisableSystemFence",
-                     "algorithmic_bytes_per_launch": round(lk_frame * bytes_per_lookup),
-                     "bytes_per_lookup": bytes_per_lookup,
-                     "traffic_note": "HBM bytes per launch: calibrated rocprofv3 FETCH_SIZE + "
-                                     "WRITE_SIZE recorded in profiles/render_traffic.json for "
-                                     "this kernel source and config (null if either changed)"},
+        "roofline": roofline(recorded_counters(traffic_key), alg, render_ms, lk_frame,
+                             bytes_per_lookup),
         "cpu_baseline": cpu,
         # HIP-event time from each timed frame's start to the next one's
         "frame_ms": {"median": round(float(np.median(frame_ms)), 4),
                      "p90": round(float(np.percentile(frame_ms, 90)), 4)},
     }
-    if not args.no_ceiling:
-        line["gather_ceiling"] = gather_ceiling(cf, torch, np, w, vol, p,
-                                                range(args.warmup, total)[:20], render_ms,
-                                                lk_frame * bytes_per_lookup)
+    if not args.no_replay:
+        line["offset_replay"] = offset_replay(cf, torch, np, w, vol, p,
+                                              range(TIMED_FIRST, TIMED_FIRST + 4))
     if not args.no_served:
         del cur, hist, vol
         torch.cuda.empty_cache()

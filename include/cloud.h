@@ -43,7 +43,7 @@ extern "C" {
 /* Raised whenever a struct layout or a signature changes (2: brick_log2 in
  * cloud_volume, queues in cloud_serve_config, depth/trace/ceiling/composite
  * entry points). */
-#define CLOUD_ABI_VERSION 2
+#define CLOUD_ABI_VERSION 3
 
 enum {
   CLOUD_OK = 0,
@@ -280,29 +280,53 @@ int cloud_count_lookups(const cloud_volume* volume, const cloud_camera* camera,
  * aligned, caller-owned) gets per pixel the number of primary samples taken
  * (up to the early exit, Section 1) and a mask whose bit i is set when
  * sample i ran the light march (density > 0). Requires params->steps <= 32.
- * Writes no image. Input to cloud_gather_ceiling. */
+ * Writes no image. Input to cloud_gather_record. */
 int cloud_lookup_trace(const cloud_volume* volume, const cloud_camera* cameras,
                        int32_t n_views, const cloud_params* params,
                        uint32_t frame_index, int32_t width, int32_t height,
                        uint32_t* out_trace, void* hip_stream);
 
-/* Measurement only: the render's gather pattern without its arithmetic.
- * One thread per pixel on the render's launch shape and tile walk.
- *  mode 0: fetches exactly the volume words cloud_render_views fetches for
- *          the lookups recorded in trace (same footprints, same order, same
- *          occupancy skip), with no interpolation, lighting or integration;
- *  mode 1: the same number of lookups per pixel at uniformly random texel
- *          coordinates of the whole volume (no occupancy skip).
- * out_rgba (device [n_views][height][width][4] float32, 16-byte aligned)
- * gets an XOR of the fetched words in .x (no meaning; it keeps every fetch)
- * and zeros. trace: as written by cloud_lookup_trace with the same volume,
- * cameras, params and frame. No detail volume; params->steps <= 32. Loop
- * counts are bounded by the step counts whatever trace holds. */
-int cloud_gather_ceiling(const cloud_volume* volume, const cloud_camera* cameras,
-                         int32_t n_views, const cloud_params* params,
-                         uint32_t frame_index, int32_t width, int32_t height,
-                         const uint32_t* trace, int32_t mode, float* out_rgba,
-                         void* hip_stream);
+/* Measurement only (Sections 4 and 5: the per-pixel jitter costs the render
+ * cache misses, so its achievable speed is set by its own gather pattern).
+ * Records every density lookup a cloud_render_views of these views makes, as
+ * the texel corner of the lookup's footprint, in the order each wavefront
+ * issues them. A wavefront's lookup instructions are its slots: step i's
+ * primary lookup while any of its lanes still marches, then the light
+ * march's lookups if any lane ran it at step i.
+ *  codes: device uint32 [n_waves][max_slots][64], n_waves = n_views *
+ *         ceil(width/16) * ceil(height/16) * 4 (wavefronts in the render's
+ *         block order, view-major); per lane of a slot kx | ky << 10 |
+ *         kz << 20, with bit 30 set when the occupancy skip redirects the
+ *         fetch to entry 0, or 0xFFFFFFFF when the lane makes no lookup in
+ *         the slot. Slots past a wavefront's count are not written.
+ *  slot_counts: device uint32 [n_waves], the slots each wavefront used.
+ *  max_slots >= steps * (1 + light_steps); trace from cloud_lookup_trace for
+ *  the same volume, cameras, params and frame (8-byte aligned).
+ * Volumes of at most 1024 texels per axis, no detail volume, steps <= 32. */
+int cloud_gather_record(const cloud_volume* volume, const cloud_camera* cameras,
+                        int32_t n_views, const cloud_params* params,
+                        uint32_t frame_index, int32_t width, int32_t height,
+                        const uint32_t* trace, int32_t max_slots, uint32_t* codes,
+                        uint32_t* slot_counts, void* hip_stream);
+
+/* Measurement only: the gather ceiling of a recorded pattern. One launch on
+ * the render's launch shape and tile walk; each wavefront takes its slots in
+ * order and fetches the volume words of each lane's corner (the entry index
+ * of the volume's layout; entry 0 for a redirected corner), with no camera,
+ * jitter, ray-box, light-path, interpolation or lighting arithmetic:
+ *  mode 0: the recorded corners;
+ *  mode 1: a uniformly random corner of the whole volume for each recorded
+ *          lookup (same slots and lanes, no redirect).
+ * blocks_per_cu caps resident workgroups per CU (0: no cap; a cap the device
+ * cannot reach with LDS is CLOUD_E_INVALID). out: device uint32
+ * [n_waves][64], an XOR of the words each lane fetched (no meaning; it keeps
+ * every fetch). volume: the one the codes were recorded on, in any layout.
+ * Corners are clamped into the volume and slot counts to max_slots whatever
+ * the buffers hold. */
+int cloud_gather_replay(const cloud_volume* volume, int32_t n_views, int32_t width,
+                        int32_t height, const uint32_t* codes, int32_t max_slots,
+                        const uint32_t* slot_counts, int32_t mode, int32_t blocks_per_cu,
+                        uint32_t* out, void* hip_stream);
 
 /* Device bytes a copy of the dense volume's base needs in `layout`. */
 int cloud_volume_packed_bytes(const cloud_volume* dense, int32_t layout,

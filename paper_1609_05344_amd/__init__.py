@@ -13,7 +13,9 @@ from ._lib import (  # noqa: F401
     cloud_check_buffer,
     cloud_count_lookups,
     cloud_lookup_trace,
-    cloud_gather_ceiling,
+    cloud_gather_record,
+    cloud_gather_replay,
+    gather_waves,
     cloud_jitter_offsets,
     cloud_march_rays,
     cloud_render,

@@ -59,7 +59,7 @@ class cloud_params(ctypes.Structure):
 _lib = None
 
 
-ABI_VERSION = 2   # the struct layouts and signatures this binding marshals
+ABI_VERSION = 3   # the struct layouts and signatures this binding marshals
 
 
 def load():
@@ -109,15 +109,19 @@ def load():
     lib.cloud_lookup_trace.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,
                                        POINTER(cloud_params), c_uint32, c_int32, c_int32,
                                        c_void_p, c_void_p]
-    lib.cloud_gather_ceiling.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,
-                                         POINTER(cloud_params), c_uint32, c_int32, c_int32,
-                                         c_void_p, c_int32, c_void_p, c_void_p]
+    lib.cloud_gather_record.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,
+                                        POINTER(cloud_params), c_uint32, c_int32, c_int32,
+                                        c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.cloud_gather_replay.argtypes = [POINTER(cloud_volume), c_int32, c_int32, c_int32,
+                                        c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p,
+                                        c_void_p]
     lib.cloud_volume_packed_bytes.argtypes = [POINTER(cloud_volume), c_int32, POINTER(c_uint64)]
     lib.cloud_volume_pack.argtypes = [POINTER(cloud_volume), c_int32, c_void_p, c_uint64,
                                       POINTER(cloud_volume), c_void_p]
     for name in ("cloud_render", "cloud_render_views", "cloud_march_rays", "cloud_taa_resolve",
                  "cloud_jitter_offsets", "cloud_check_buffer", "cloud_count_lookups",
-                 "cloud_lookup_trace", "cloud_gather_ceiling", "cloud_render_depth",
+                 "cloud_lookup_trace", "cloud_gather_record", "cloud_gather_replay",
+                 "cloud_render_depth",
                  "cloud_taa_resolve_reproject", "cloud_composite",
                  "cloud_volume_packed_bytes", "cloud_volume_pack", "cloud_tune"):
         getattr(lib, name).restype = c_int
@@ -352,17 +356,49 @@ def cloud_lookup_trace(volume: Volume, cameras, params, frame_index: int, width:
     return out
 
 
-def cloud_gather_ceiling(volume: Volume, cameras, params, frame_index: int, width: int,
-                         height: int, trace, mode: int = 0, out=None, stream=None):
-    """Fetch-only replay of the render's lookups (mode 0) or as many uniformly
-    random lookups (mode 1); returns the [n_views, H, W, 4] output buffer."""
+def gather_waves(n_views: int, width: int, height: int) -> int:
+    """Wavefronts of a render of n_views width x height views (four per 16x16 tile)."""
+    return n_views * ((width + 15) // 16) * ((height + 15) // 16) * 4
+
+
+def cloud_gather_record(volume: Volume, cameras, params, frame_index: int, width: int,
+                        height: int, trace, max_slots: int = 0, codes=None, slot_counts=None,
+                        stream=None):
+    """The render's lookups as per-wavefront slots of corner codes; returns
+    (codes [n_waves, max_slots, 64] int32 (uint32 bits), slot_counts [n_waves]
+    int32). max_slots 0: steps * (1 + light_steps)."""
+    import torch
     n = len(cameras)
-    out = _out(out, (n, height, width, 4), volume.base.device)
+    if max_slots <= 0:
+        max_slots = int(params.steps) * (1 + int(params.light_steps))
+    waves = gather_waves(n, width, height)
+    dev = volume.base.device
+    if codes is None:
+        codes = torch.empty((waves, max_slots, 64), dtype=torch.int32, device=dev)
+    if slot_counts is None:
+        slot_counts = torch.empty((waves,), dtype=torch.int32, device=dev)
     cams = (cloud_camera * max(n, 1))(*[make_camera(c) for c in cameras])
     prm = make_params(params)
-    check(load().cloud_gather_ceiling(ctypes.byref(volume.struct), cams, n, ctypes.byref(prm),
-                                      int(frame_index) & 0xFFFFFFFF, int(width), int(height),
-                                      _ptr(trace), int(mode), _ptr(out), _stream(stream)))
+    check(load().cloud_gather_record(ctypes.byref(volume.struct), cams, n, ctypes.byref(prm),
+                                     int(frame_index) & 0xFFFFFFFF, int(width), int(height),
+                                     _ptr(trace), int(max_slots), _ptr(codes), _ptr(slot_counts),
+                                     _stream(stream)))
+    return codes, slot_counts
+
+
+def cloud_gather_replay(volume: Volume, n_views: int, width: int, height: int, codes,
+                        slot_counts, mode: int = 0, blocks_per_cu: int = 0, out=None,
+                        stream=None):
+    """Fetch-only replay of recorded slots (mode 0) or of as many uniformly
+    random corners (mode 1); returns the [n_waves, 64] int32 XOR output."""
+    import torch
+    waves = gather_waves(n_views, width, height)
+    max_slots = int(codes.shape[1]) if codes.dim() == 3 else int(codes.numel() // (waves * 64))
+    if out is None:
+        out = torch.empty((waves, 64), dtype=torch.int32, device=volume.base.device)
+    check(load().cloud_gather_replay(ctypes.byref(volume.struct), int(n_views), int(width),
+                                     int(height), _ptr(codes), max_slots, _ptr(slot_counts),
+                                     int(mode), int(blocks_per_cu), _ptr(out), _stream(stream)))
     return out
 
 

@@ -408,43 +408,102 @@ int cloud_lookup_trace(const cloud_volume* volume, const cloud_camera* cameras, 
   CLOUD_GUARD_END
 }
 
-int cloud_gather_ceiling(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
-                         const cloud_params* params, uint32_t frame_index, int32_t width,
-                         int32_t height, const uint32_t* trace, int32_t mode, float* out_rgba,
-                         void* hip_stream) {
+// Wavefronts of a render of n_views W x H views: four per 16x16 tile.
+static size_t render_waves(int W, int H, int n_views) {
+  return (size_t)((W + 15) / 16) * ((H + 15) / 16) * 4 * (size_t)n_views;
+}
+
+static int check_replay_volume(const cloud_volume* volume, DevVolume* v, int* dtype) {
+  if (!volume) return fail(CLOUD_E_INVALID, "volume is NULL");
+  if (volume->detail) return fail(CLOUD_E_INVALID, "the gather replay takes no detail volume");
+  int rc = prepare_volume(volume, v, dtype);
+  if (rc) return rc;
+  if (v->nx > 1024 || v->ny > 1024 || v->nz > 1024)
+    return fail(CLOUD_E_INVALID, "the gather replay codes corners of at most 1024 texels per axis");
+  return CLOUD_OK;
+}
+
+static int check_codes(const uint32_t* codes, const uint32_t* slot_counts, int max_slots,
+                       size_t waves) {
+  if (max_slots < 1) return fail(CLOUD_E_INVALID, "max_slots must be >= 1");
+  if (reinterpret_cast<uintptr_t>(codes) % 4 || reinterpret_cast<uintptr_t>(slot_counts) % 4)
+    return fail(CLOUD_E_INVALID, "codes and slot_counts must be 4-byte aligned");
+  int rc = check_span(codes, waves * (size_t)max_slots * 256, "codes");
+  if (rc) return rc;
+  return check_span(slot_counts, waves * 4, "slot_counts");
+}
+
+int cloud_gather_record(const cloud_volume* volume, const cloud_camera* cameras, int32_t n_views,
+                        const cloud_params* params, uint32_t frame_index, int32_t width,
+                        int32_t height, const uint32_t* trace, int32_t max_slots, uint32_t* codes,
+                        uint32_t* slot_counts, void* hip_stream) {
   CLOUD_GUARD_BEGIN
   clear_error();
   if (!cameras) return fail(CLOUD_E_INVALID, "cameras is NULL");
   if (n_views < 1) return fail(CLOUD_E_INVALID, "n_views must be >= 1");
-  if (mode != 0 && mode != 1) return fail(CLOUD_E_INVALID, "mode must be 0 or 1");
   int rc = check_image(width, height, n_views);
   if (rc) return rc;
-  if (!volume) return fail(CLOUD_E_INVALID, "volume is NULL");
-  if (volume->detail) return fail(CLOUD_E_INVALID, "the gather ceiling takes no detail volume");
   DevVolume v;
   int dtype;
-  if ((rc = prepare_volume(volume, &v, &dtype))) return rc;
+  if ((rc = check_replay_volume(volume, &v, &dtype))) return rc;
   DevParams p;
   if ((rc = prepare_params(params, volume, &p))) return rc;
   if (params->steps > 32) return fail(CLOUD_E_INVALID, "a lookup trace needs steps <= 32");
+  if ((long long)max_slots < (long long)params->steps * (1 + params->light_steps))
+    return fail(CLOUD_E_INVALID, "max_slots must be >= steps * (1 + light_steps)");
   const size_t px = (size_t)width * height;
   if (reinterpret_cast<uintptr_t>(trace) % 8) return fail(CLOUD_E_INVALID, "trace must be 8-byte aligned");
   if ((rc = check_span(trace, px * 8 * (size_t)n_views, "trace"))) return rc;
-  if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
-    return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
-  if ((rc = check_span(out_rgba, px * 16 * (size_t)n_views, "out_rgba"))) return rc;
+  if ((rc = check_codes(codes, slot_counts, max_slots, render_waves(width, height, n_views))))
+    return rc;
+  const size_t view_waves = render_waves(width, height, 1);
   DevCameras cams;
   for (int i = 0; i < n_views; ++i) {
     if ((rc = prepare_camera(&cameras[i], width, height, &cams.c[i % kMaxViews]))) return rc;
     if ((i + 1) % kMaxViews == 0 || i + 1 == n_views) {
       const int first = i - i % kMaxViews;
-      hipError_t e = launch_ceiling(v, dtype, volume->layout, p, cams, i - first + 1, frame_index,
-                                    width, height, trace + (size_t)first * px * 2, mode == 1,
-                                    out_rgba + (size_t)first * px * 4,
-                                    static_cast<hipStream_t>(hip_stream));
-      if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("ceiling launch: ") + hipGetErrorString(e));
+      hipError_t e = launch_gather_record(
+          v, volume->layout, p, cams, i - first + 1, frame_index, width, height,
+          trace + (size_t)first * px * 2, max_slots,
+          codes + (size_t)first * view_waves * (size_t)max_slots * 64,
+          slot_counts + (size_t)first * view_waves, static_cast<hipStream_t>(hip_stream));
+      if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("record launch: ") + hipGetErrorString(e));
     }
   }
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_gather_replay(const cloud_volume* volume, int32_t n_views, int32_t width, int32_t height,
+                        const uint32_t* codes, int32_t max_slots, const uint32_t* slot_counts,
+                        int32_t mode, int32_t blocks_per_cu, uint32_t* out, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (n_views < 1) return fail(CLOUD_E_INVALID, "n_views must be >= 1");
+  if (mode != 0 && mode != 1) return fail(CLOUD_E_INVALID, "mode must be 0 or 1");
+  if (blocks_per_cu < 0 || blocks_per_cu > 64)
+    return fail(CLOUD_E_INVALID, "blocks_per_cu must be in [0, 64]");
+  int rc = check_image(width, height, n_views);
+  if (rc) return rc;
+  DevVolume v;
+  int dtype;
+  if ((rc = check_replay_volume(volume, &v, &dtype))) return rc;
+  const size_t waves = render_waves(width, height, n_views);
+  if (waves / 4 > 0x7FFFFFFF) return fail(CLOUD_E_INVALID, "too many tiles for one launch");
+  if ((rc = check_codes(codes, slot_counts, max_slots, waves))) return rc;
+  if (reinterpret_cast<uintptr_t>(out) % 4) return fail(CLOUD_E_INVALID, "out must be 4-byte aligned");
+  if ((rc = check_span(out, waves * 64 * 4, "out"))) return rc;
+  // the replay addresses the stored base through a 32-bit buffer range
+  size_t bytes = 0;
+  if ((rc = volume_layout_bytes(volume, volume->layout, &bytes))) return rc;
+  if (bytes > 0xFFFFFF00ull)
+    return fail(CLOUD_E_INVALID, "the gather replay needs a stored volume below 4 GiB");
+  hipError_t e = launch_gather_replay(v, dtype, volume->layout, (uint32_t)((bytes + 15) & ~15ull),
+                                      (int)(waves / 4), max_slots, codes, slot_counts, mode == 1,
+                                      blocks_per_cu, out, static_cast<hipStream_t>(hip_stream));
+  if (e == hipErrorInvalidValue)
+    return fail(CLOUD_E_INVALID, "blocks_per_cu cannot be reached on this device");
+  if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("replay launch: ") + hipGetErrorString(e));
   return CLOUD_OK;
   CLOUD_GUARD_END
 }

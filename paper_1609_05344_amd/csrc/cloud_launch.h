@@ -39,9 +39,6 @@ TileWalk tile_walk();
 // when blocks_per_cu <= 0; -1 when the cap cannot be reached this way).
 long long residency_lds(int blocks_per_cu, size_t static_lds);
 
-// Resident workgroups per CU of the render kernel for this volume under the
-// current tuning (the ceiling kernel is run at the same residency).
-int render_residency(int dtype, int layout, bool detail);
 
 // Render n_views (<= kMaxViews) cameras into out [n_views][H][W][4]. With
 // counts or trace given, store no image: add the density lookups to *counts
@@ -65,9 +62,15 @@ hipError_t launch_taa_reproject(const float* cur, const float* depth, const floa
 // Fetch-only replay of a render's lookups (random == false: the positions
 // recorded in trace; random == true: as many lookups per pixel at uniformly
 // random footprints of the volume) into out [n_views][H][W][4].
-hipError_t launch_ceiling(const DevVolume& v, int dtype, int layout, const DevParams& p,
-                          const DevCameras& c, int n_views, uint32_t frame, int W, int H,
-                          const uint32_t* trace, bool random, float* out, hipStream_t s);
+// Record the render's lookups of n_views (<= kMaxViews) views as corner
+// codes per wavefront slot, and replay recorded codes (see ceiling.hip).
+hipError_t launch_gather_record(const DevVolume& v, int layout, const DevParams& p,
+                                const DevCameras& c, int n_views, uint32_t frame, int W, int H,
+                                const uint32_t* trace, int max_slots, uint32_t* codes,
+                                uint32_t* counts, hipStream_t s);
+hipError_t launch_gather_replay(const DevVolume& v, int dtype, int layout, uint32_t bytes,
+                                int tiles, int max_slots, const uint32_t* codes, const uint32_t* counts,
+                                bool random, int blocks_per_cu, uint32_t* out, hipStream_t s);
 
 // March n explicit rays into out [n][4].
 hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParams& p,

@@ -287,26 +287,6 @@ static int render_cap() {
   return tuning().render_blocks_per_cu;
 }
 
-template <int DT, int LAYOUT, bool DETAIL>
-static int residency_of() {
-  const void* fn = reinterpret_cast<const void*>(render_kernel<DT, LAYOUT, DETAIL, kImage>);
-  static const size_t slds = static_lds_of(render_kernel<DT, LAYOUT, DETAIL, kImage>);
-  const long long pad = residency_lds(render_cap<DT, LAYOUT>(), slds);
-  int n = 0;
-  if (pad < 0 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, (size_t)pad) != hipSuccess)
-    return 0;
-  return n;
-}
-
-struct ResidencyQuery {
-  template <int DT, int LAYOUT, bool DETAIL, int MODE>
-  hipError_t run() {
-    n = residency_of<DT, LAYOUT, DETAIL>();
-    return hipSuccess;
-  }
-  int n = 0;
-};
-
 struct RenderLaunch {
   const DevVolume& v;
   const DevParams& p;
@@ -365,12 +345,6 @@ hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevPar
   RenderLaunch f{v, p, c, n_views, frame, W, H, out, counts, trace, depth, s};
   const int mode = counts != nullptr || trace != nullptr ? kCount : depth != nullptr ? kDepth : kImage;
   return dispatch(dtype, sampler_layout(v, layout), v.detail != nullptr, mode, f);
-}
-
-int render_residency(int dtype, int layout, bool detail) {
-  ResidencyQuery q;
-  if (dispatch(dtype, layout, detail, kImage, q) != hipSuccess) return 0;
-  return q.n;
 }
 
 hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParams& p,

@@ -37,7 +37,7 @@ def test_exports_every_declared_function(lib):
     assert len(names) >= 6
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.cloud_abi_version() == _lib.ABI_VERSION == 2
+    assert lib.cloud_abi_version() == _lib.ABI_VERSION == 3
 
 
 def test_struct_layout_matches_header(tmp_path):

@@ -1,5 +1,5 @@
 """bench.py pieces that need no GPU: the one-GPU guard, the counter record
-lookup and the VALU fraction."""
+lookup, the roofline object and the fixed timed window."""
 
 import json
 import os
@@ -23,23 +23,42 @@ def test_counter_record_applies_only_to_its_sources_and_config():
     with open(bench.TRAFFIC_FILE) as f:
         rec = json.load(f)
     cfg = rec["config"]
+    got = bench.recorded_counters(cfg).get("traffic_bytes_per_launch")
     if rec["source_sha1"] == bench.kernel_source_sha1():
-        assert bench.recorded_traffic(cfg) == rec["traffic_bytes_per_launch"]
+        assert got == rec["traffic_bytes_per_launch"]
     else:
-        assert bench.recorded_traffic(cfg) is None
+        assert got is None
     # filed under the key the default bench run looks up (H, FP32, quad, occupancy)
     assert cfg == bench.counter_config("H", "f32", "quad", True)
     other = dict(cfg, dtype="bf16")
-    assert bench.recorded_traffic(other) is None
     assert bench.recorded_counters(other) == {}
 
 
-def test_valu_fraction():
-    assert bench.valu_fraction({}, 0.2) is None
-    v = bench.valu_fraction({"valu_insts_per_launch": 1_000_000}, 1.0)
-    # 1e6 wave instructions x 64 lanes in 1 ms, against 256 x 64 x 2.4e9 lane-instr/s
-    assert abs(v["frac"] - 64e9 / (256 * 64 * 2.4e9)) < 1e-4
-    assert v["peak"] == round(256 * 64 * 2.4e9 / 1e12, 2)
+def test_roofline_fractions():
+    alg = {"ops_per_launch": 3.0e9, "units_per_launch": {}, "ops_per_unit": {}}
+    rec = {"traffic_bytes_per_launch": 800_000_000, "valu_insts_per_launch": 50_000_000}
+    r = bench.roofline(rec, alg, 0.2, 1e6, 32)
+    peak = 256 * 64 * 2.4e9
+    # 3e9 lane operations in 0.2 ms against 256 x 64 x 2.4e9 per second
+    assert r["bound"] == "alu" and abs(r["frac"] - 3e9 / 2e-4 / peak) < 1e-4
+    assert abs(r["achieved"] - 3e9 / 2e-4 / 1e12) < 1e-3
+    assert abs(r["hbm"]["frac"] - 8e8 / 2e-4 / 8e12) < 1e-4
+    assert abs(r["valu_issued"]["frac"] - 5e7 * 64 / 2e-4 / peak) < 1e-4
+    assert r["traffic"] == 800_000_000
+    empty = bench.roofline({}, None, 0.2, 1e6, 32)
+    assert empty["frac"] is None and empty["hbm"] is None and empty["valu_issued"] is None
+
+
+def test_timed_window_does_not_depend_on_warmup_or_steps():
+    # the driver's --steps 20 --warmup 5 and the defaults time the same frames
+    a, b = bench.timed_frames(20), bench.timed_frames(300)
+    assert sorted(set(a)) == sorted(set(b)) == list(range(bench.TIMED_FIRST,
+                                                          bench.TIMED_FIRST + bench.TIMED_PERIOD))
+    assert all(b.count(f) == 300 // bench.TIMED_PERIOD for f in set(b))
+    assert bench.warm_frames(5) == list(range(bench.TIMED_FIRST - 5, bench.TIMED_FIRST))
+    assert bench.warm_frames(200)[-1] == bench.TIMED_FIRST - 1
+    big = bench.warm_frames(bench.TIMED_FIRST + 7)
+    assert min(big) >= 0 and max(big) < bench.TIMED_FIRST and big[-1] == bench.TIMED_FIRST - 1
 
 
 def test_oracle_subset_counts_the_subset_lookups():

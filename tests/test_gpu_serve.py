@@ -205,3 +205,27 @@ def test_fp16_oct_server_1080p(cf):
                         frame=0, pixels=pix)
         got = to_np(outs[s])[pix[:, 1], pix[:, 0]]
         assert max_err(got, want) < HALF_TOL
+
+
+def test_poll_with_a_huge_max_returns_a_code(cf, vol):
+    """cloud_serve_poll allocates nothing that grows with max: an idle
+    server, and one with two finished requests, polled with the largest max
+    into a small array, return CLOUD_OK with the right counts."""
+    import ctypes
+    import torch
+    from paper_1609_05344_amd import _lib
+    say("serve: poll with max = 2^31 - 1")
+    w = scenes.workload("C2")
+    outs = [torch.zeros((32, 32, 4), device="cuda") for _ in range(2)]
+    arr = (_lib.cloud_completion * 8)()
+    n = ctypes.c_int32(-1)
+    with cf.Server(vol, budget_bytes=1 << 30) as srv:
+        rc = srv.lib.cloud_serve_poll(srv.handle, arr, 2**31 - 1, ctypes.byref(n))
+        assert rc == 0 and n.value == 0
+        ids = [srv.submit(s, w.camera(s), w.params, 32, 32, 0, outs[s]) for s in range(2)]
+        while srv.stats()["completed"] < 2:
+            srv.wait(0.05)
+        rc = srv.lib.cloud_serve_poll(srv.handle, arr, 2**31 - 1, ctypes.byref(n))
+        assert rc == 0 and n.value == 2
+        assert sorted(arr[i].request_id for i in range(2)) == sorted(ids)
+        assert all(arr[i].status == 0 for i in range(2))

@@ -469,10 +469,10 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
     lat, done_t = [], []
 
     def camera(s, f):
-        # the same stretch of the orbit (frames 10..69) that the plain leg times
+        # the same window of orbit frames that the plain leg times
         if w.views > 1:
-            return w.camera(10 + f % 60, view=s % w.views)
-        return w.camera(10 + (s + f) % 60)
+            return w.camera(TIMED_FIRST + f % TIMED_PERIOD, view=s % w.views)
+        return w.camera(TIMED_FIRST + (s + f) % TIMED_PERIOD)
 
     with cf.Server(vol, budget_bytes=n_streams * W * H * 40, max_batch=64, queues=queues,
                    use_graphs=graphs) as srv:
@@ -703,6 +703,10 @@ def main():
                     help="comma-separated total arrival rates (req/s): run only the open-loop "
                          "64-stream serving load at each rate and print one JSON line")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the open-loop 64-stream serving leg of the default line")
+    ap.add_argument("--c4-seconds", type=float, default=3.0,
+                    help="measured seconds per rate of the default line's open-loop leg")
     ap.add_argument("--quality", action="store_true",
                     help="print the precision-form and step-count error report instead")
     ap.add_argument("--cpu-frames", type=int, default=36)
@@ -908,6 +912,16 @@ def main():
         served["plain_frames_per_s"] = round(V * 1e3 / ms_per_step, 1)
         served["speedup_vs_plain"] = round(served["frames_per_s"] * ms_per_step / (1e3 * V), 3)
         line["served"] = served
+    if not args.no_served and not args.no_c4:
+        # the serving form's latency metric: 64 streams of mixed resolutions and
+        # step counts, open-loop Poisson arrivals at the specified total rate,
+        # and at half of it
+        line["served_c4"] = {
+            "workload": "64 streams, resolutions in {640x360,1280x720,1920x1080,3840x2160}, "
+                        "steps in {8,16,32,128}, shared f16 256^3 (oct layout, occupancy), TAA "
+                        "per stream, Poisson arrivals",
+            "runs": [served_poisson(cf, scenes, torch, r, args.c4_seconds, warm_s=1.0,
+                                    queues=args.serve_queues) for r in (2000.0, 1000.0)]}
     print(json.dumps(line), flush=True)
 
 

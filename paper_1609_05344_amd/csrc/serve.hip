@@ -48,12 +48,16 @@ __device__ __forceinline__ int find_item(const ServeTable* tab, int n_items, int
   return __builtin_amdgcn_readfirstlane(lo);
 }
 
-// Persistent render over every tile of every request in the batch. The tile
-// sequence (requests back to back, each in super-tile order) is cut into 8
-// contiguous ranges, one per XCD (workgroups are dealt to XCDs round-robin,
-// so blockIdx % 8 names the XCD a workgroup most likely runs on); a
-// workgroup drains its own range first, then helps the others, so neighbouring
-// tiles tend to share an L2. Every workgroup leaves once all ranges are empty.
+// Persistent render over every tile of every request in the batch. The
+// batch's tiles (requests back to back, each in super-tile order) are walked
+// as the plain render walks one launch's tiles: block b of the walk covers
+// tile xcd_walk(b), and the dispatcher would hand block b to XCD b % 8. Here
+// the workgroups of XCD x (blockIdx % 8 names the XCD a workgroup most likely
+// runs on) take the blocks b = x, x + 8, x + 16, ... in order from the XCD's
+// own counter, so each XCD covers the same tiles, in the same order, as in a
+// plain launch: compact runs that share its L2, spread over the batch for
+// balance. A workgroup whose sequence is empty helps the other XCDs'; every
+// workgroup leaves once all eight are empty.
 // The table is read-only here apart from its work counters, which come in as
 // their own pointer: with the table const and unaliased, the request fields
 // are scalar loads held in scalar registers rather than per-lane copies.
@@ -62,20 +66,22 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol,
                                                            unsigned int* __restrict__ counters,
                                                            const ServeTable* __restrict__ tab) {
   stage_volume<LAYOUT>(vol);
-  __shared__ int s_tile;
+  __shared__ int s_block;
   const int total = tab->total_tiles, n_items = tab->n_items, S = tab->supertile;
+  const int L = tab->xcd_run;
   const int home = blockIdx.x & 7;
   for (int probe = 0; probe < 8;) {
     const int q = (home + probe) & 7;
-    const int b = (int)(((long long)total * q) >> 3), e = (int)(((long long)total * (q + 1)) >> 3);
-    if (threadIdx.x == 0) s_tile = b + (int)atomicAdd(&counters[q * kCounterStride], 1u);
+    const int n_q = (total - q + 7) >> 3;   // blocks b < total with b % 8 == q
+    if (threadIdx.x == 0) s_block = (int)atomicAdd(&counters[q * kCounterStride], 1u);
     __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(s_tile);
+    const int k = __builtin_amdgcn_readfirstlane(s_block);
     __syncthreads();
-    if (t >= e) {
+    if (k >= n_q) {
       ++probe;
       continue;
     }
+    const int t = xcd_walk(8 * k + q, total, L);
     const int i = find_item(tab, n_items, t);
     const ServeItem& it = tab->items[i];
     int tx, ty;
@@ -292,7 +298,9 @@ class HipExecutor : public serve::Executor {
     t->total_taa_tiles = taa_tile;
     t->n_items = (int)items.size();
     t->blend = blend_;
-    t->supertile = tile_walk().S;
+    const TileWalk tw = tile_walk();
+    t->supertile = tw.S;
+    t->xcd_run = tw.L;
     hipError_t e;
     if (graphs_) {
       e = hipGraphLaunch(exec_[slot], queue(slot));

@@ -43,6 +43,7 @@ struct ServeTable {
   int n_items;
   float blend;
   int supertile;
+  int xcd_run;                  // tiles per XCD run of the render's walk (xcd_walk)
   ServeItem items[kMaxBatch];
 };
 

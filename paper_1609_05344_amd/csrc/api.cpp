@@ -150,6 +150,10 @@ int prepare_volume(const cloud_volume* v, DevVolume* out, int* dtype) {
     d.bx = b[0];
     d.by = b[1];
     d.bz = b[2];
+    const int corners = v->layout == CLOUD_LAYOUT_OCT ? 8 : 4;
+    d.entry_shift = corners * (int)dtype_size(v->dtype) == 32 ? 5 : corners * (int)dtype_size(v->dtype) == 16 ? 4 : 3;
+    d.tab = tab_fits(v->nx, v->ny, v->nz) && bytes <= 0xFFFFFF00ull ? 1 : 0;
+    d.tab_bytes = d.tab ? (uint32_t)bytes : 0u;
   }
   const int n[3] = {v->nx, v->ny, v->nz};
   float* s[3] = {&d.sx, &d.sy, &d.sz};

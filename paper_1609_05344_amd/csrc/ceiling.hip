@@ -162,11 +162,10 @@ struct ReplayQuad {
   __device__ static __forceinline__ void offsets(const DevVolume& v, int kx, int ky, int kz,
                                                  bool live, bool take, uint32_t skip,
                                                  uint32_t (&o)[kLoads]) {
-    constexpr uint32_t E = DT == DT_F32 ? 16 : 8;
-    const uint32_t ia = (uint32_t)packed_entry<TAB>(v, kx, ky, kz);
-    const uint32_t ib = (uint32_t)packed_entry<TAB>(v, kx, ky, min(kz + 1, v.nz - 1));
-    o[0] = !take ? skip : live ? ia * E : 0u;
-    o[1] = !take ? skip : live ? ib * E : 0u;
+    entry_off_t<TAB> ia, ib;   // below 4 GiB: checked on the host
+    quad_entries<TAB>(v, kx, ky, kz, ia, ib);
+    o[0] = !take ? skip : live ? (uint32_t)ia : 0u;
+    o[1] = !take ? skip : live ? (uint32_t)ib : 0u;
   }
   __device__ static __forceinline__ uint32_t fetch(const ReplaySource& src,
                                                    const uint32_t (&o)[kLoads]) {
@@ -191,9 +190,8 @@ struct ReplayOct {
   __device__ static __forceinline__ void offsets(const DevVolume& v, int kx, int ky, int kz,
                                                  bool live, bool take, uint32_t skip,
                                                  uint32_t (&o)[kLoads]) {
-    constexpr uint32_t E = DT == DT_F32 ? 32 : 16;
     const uint32_t e = (uint32_t)packed_entry<TAB>(v, kx, ky, kz + 1);
-    o[0] = !take ? skip : live ? e * E : 0u;
+    o[0] = !take ? skip : live ? e : 0u;
     if constexpr (kLoads == 2) o[1] = !take ? skip : o[0] + 16u;
   }
   __device__ static __forceinline__ uint32_t fetch(const ReplaySource& src,

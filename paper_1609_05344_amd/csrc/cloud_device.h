@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "cloud_types.h"
 
 namespace cloud {
@@ -100,26 +102,36 @@ __device__ __forceinline__ void split_coord(float f, int n, float& w, int& k) {
 
 static __shared__ uint32_t s_occupancy[kOccupancyWords];
 
-// Entry-index terms of a table-indexed packed volume (kLayoutTab): entry
-// (x + 1, y + 1, z) of packed_index is s_terms[x] + s_terms[kTabAxis + y] +
-// s_terms[2 kTabAxis + z], for corners x, y and packed planes z.
-static __shared__ int s_terms[3 * kTabAxis];
+// Byte-offset terms of a table-indexed packed volume (kLayoutTab): the bytes
+// of entry (x + 1, y + 1, z) of packed_index are s_terms[x] +
+// s_terms[kTabAxis + y] + s_terms[2 kTabAxis + z], for corners x, y and
+// packed planes z; for the quad layout s_terms[3 kTabAxis + z] is the z term
+// of the next plane up, min(z + 1, nz - 1), so that both planes of a lookup
+// come from one table address.
+static __shared__ uint32_t s_terms[4 * kTabAxis];
 
-__device__ __forceinline__ int packed_term(int i, int sh, int stride, int low_shift) {
-  return (mul24(i >> sh, stride) << 3) | ((i & ((1 << sh) - 1)) << low_shift);
+__device__ __forceinline__ uint32_t packed_term(int i, int sh, int stride, int low_shift,
+                                                int entry_shift) {
+  return (uint32_t)((mul24(i >> sh, stride) << 3) | ((i & ((1 << sh) - 1)) << low_shift))
+         << entry_shift;
 }
 
-// Entry-index terms of a table-indexed packed layout into LDS (no barrier).
+// Byte-offset terms of a table-indexed packed layout into LDS (no barrier).
 template <int LAYOUT>
 __device__ __forceinline__ void build_terms(const DevVolume& v) {
   if constexpr ((LAYOUT & kLayoutTab) != 0) {
-    // packed planes: 0..nz-1 (quad), 0..nz (oct); the host checked tab_fits
+    // packed planes: 0..nz-1 (quad), 0..nz (oct); the host checked v.tab
     const int planes = (LAYOUT & 3) == LAYOUT_OCT ? v.nz + 1 : v.nz;
-    for (int i = threadIdx.x; i < v.nx; i += blockDim.x) s_terms[i] = packed_term(i + 1, v.bx, 1, 0);
+    const int es = v.entry_shift;
+    for (int i = threadIdx.x; i < v.nx; i += blockDim.x) s_terms[i] = packed_term(i + 1, v.bx, 1, 0, es);
     for (int i = threadIdx.x; i < v.ny; i += blockDim.x)
-      s_terms[kTabAxis + i] = packed_term(i + 1, v.by, v.row, v.bx);
+      s_terms[kTabAxis + i] = packed_term(i + 1, v.by, v.row, v.bx, es);
     for (int i = threadIdx.x; i < planes; i += blockDim.x)
-      s_terms[2 * kTabAxis + i] = packed_term(i, v.bz, v.plane, v.bx + v.by);
+      s_terms[2 * kTabAxis + i] = packed_term(i, v.bz, v.plane, v.bx + v.by, es);
+    if constexpr ((LAYOUT & 3) == LAYOUT_QUAD) {
+      for (int i = threadIdx.x; i < planes; i += blockDim.x)
+        s_terms[3 * kTabAxis + i] = packed_term(min(i + 1, planes - 1), v.bz, v.plane, v.bx + v.by, es);
+    }
   }
 }
 
@@ -190,8 +202,11 @@ struct BaseSampler;
 template <int DT>
 struct BaseSampler<DT, LAYOUT_DENSE> {
   static constexpr int kWords = 8;
-  __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
-                                              uint32_t (&w)[kWords]) {
+  struct Addr {
+    int idx[8];
+  };
+  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz,
+                                              bool live) {
     const int xa = kx, xb = min(kx + 1, v.nx - 1);
     const int ya = ky, yb = min(ky + 1, v.ny - 1);
     const int za = kz, zb = min(kz + 1, v.nz - 1);
@@ -202,11 +217,14 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
     const int i0 = live ? pa + ra : 0, i1 = live ? pa + rb : 0;
     const int i2 = live ? pb + ra : 0, i3 = live ? pb + rb : 0;
     const int x0 = live ? xa : 0, x1 = live ? xb : 0;
-    const int idx[8] = {i0 + x0, i0 + x1, i1 + x0, i1 + x1, i2 + x0, i2 + x1, i3 + x0, i3 + x1};
+    return {{i0 + x0, i0 + x1, i1 + x0, i1 + x1, i2 + x0, i2 + x1, i3 + x0, i3 + x1}};
+  }
+  __device__ static __forceinline__ void fetch(const DevVolume& v, const Addr& a,
+                                               uint32_t (&w)[kWords]) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      if constexpr (DT == DT_F32) w[k] = static_cast<const uint32_t*>(v.base)[idx[k]];
-      else w[k] = static_cast<const uint16_t*>(v.base)[idx[k]];
+      if constexpr (DT == DT_F32) w[k] = static_cast<const uint32_t*>(v.base)[a.idx[k]];
+      else w[k] = static_cast<const uint16_t*>(v.base)[a.idx[k]];
     }
   }
   __device__ static __forceinline__ void decode(const uint32_t (&w)[kWords], float (&c)[8]) {
@@ -225,12 +243,59 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
   }
 };
 
-// Entry of the footprint with corner k (kx, ky in [0, n - 1]) in packed
-// plane z of a packed volume: three LDS terms (TAB) or the index arithmetic.
+// Byte offsets into a packed volume: 32-bit with the LDS tables (the host
+// admits table-indexed volumes below 4 GiB), 64-bit otherwise.
 template <bool TAB>
-__device__ __forceinline__ int packed_entry(const DevVolume& v, int kx, int ky, int z) {
-  if constexpr (TAB) return s_terms[kx] + s_terms[kTabAxis + ky] + s_terms[2 * kTabAxis + z];
-  else return packed_index(kx + 1, ky + 1, z, v.bx, v.by, v.bz, v.row, v.plane);
+using entry_off_t = std::conditional_t<TAB, uint32_t, uint64_t>;
+
+// Byte offset of the entry of the footprint with corner k (kx, ky in
+// [0, n - 1]) in packed plane z of a packed volume: three LDS terms (TAB) or
+// the index arithmetic.
+template <bool TAB>
+__device__ __forceinline__ entry_off_t<TAB> packed_entry(const DevVolume& v, int kx, int ky, int z) {
+  if constexpr (TAB) {
+    return s_terms[kx] + s_terms[kTabAxis + ky] + s_terms[2 * kTabAxis + z];
+  } else {
+    return (uint64_t)(uint32_t)packed_index(kx + 1, ky + 1, z, v.bx, v.by, v.bz, v.row, v.plane)
+           << v.entry_shift;
+  }
+}
+
+// Byte offsets of the two entries (planes kz and min(kz + 1, nz - 1)) of a
+// quad-layout lookup with corner k.
+template <bool TAB>
+__device__ __forceinline__ void quad_entries(const DevVolume& v, int kx, int ky, int kz,
+                                             entry_off_t<TAB>& ea, entry_off_t<TAB>& eb) {
+  if constexpr (TAB) {
+    const uint32_t xy = s_terms[kx] + s_terms[kTabAxis + ky];
+    ea = xy + s_terms[2 * kTabAxis + kz];
+    eb = xy + s_terms[3 * kTabAxis + kz];
+  } else {
+    ea = packed_entry<false>(v, kx, ky, kz);
+    eb = packed_entry<false>(v, kx, ky, min(kz + 1, v.nz - 1));
+  }
+}
+
+// The word of type T (uint2 or uint4) at byte offset off of the volume. A
+// table-indexed volume is below 4 GiB, so its fetches are buffer loads with
+// the 32-bit offset as is (no per-lane address arithmetic); the range is the
+// stored size, which every offset stays inside.
+template <typename T, typename O>
+__device__ __forceinline__ T volume_word(const DevVolume& v, O off) {
+  if constexpr (std::is_same_v<O, uint32_t>) {
+    // word 3: the untyped-load format the gfx9 family expects
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void*>(v.base), (short)0, (int)v.tab_bytes, 0x00020000);
+    if constexpr (sizeof(T) == 16) {
+      const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+      return T{q[0], q[1], q[2], q[3]};
+    } else {
+      const auto q = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+      return T{q[0], q[1]};
+    }
+  } else {
+    return *reinterpret_cast<const T*>(static_cast<const char*>(v.base) + off);
+  }
 }
 
 // Four float32 texels, or eight 16-bit texels packed two to a word (low half
@@ -253,21 +318,23 @@ __device__ __forceinline__ void decode_packed(const uint32_t (&w)[N], float (&c)
 template <int DT, bool TAB>
 struct QuadSampler {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
-  __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
-                                              uint32_t (&w)[kWords]) {
-    const int za = kz, zb = min(kz + 1, v.nz - 1);
-    const int ia = packed_entry<TAB>(v, kx, ky, za), ib = packed_entry<TAB>(v, kx, ky, zb);
-    const int ea = live ? ia : 0;
-    const int eb = live ? ib : 0;
-    // entries are non-negative: index with 32-bit unsigned offsets
+  struct Addr {
+    entry_off_t<TAB> a, b;   // byte offsets of planes kz and kz + 1
+  };
+  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz,
+                                              bool live) {
+    entry_off_t<TAB> ia, ib;
+    quad_entries<TAB>(v, kx, ky, kz, ia, ib);
+    return {live ? ia : 0u, live ? ib : 0u};
+  }
+  __device__ static __forceinline__ void fetch(const DevVolume& v, const Addr& e,
+                                               uint32_t (&w)[kWords]) {
     if constexpr (DT == DT_F32) {
-      const uint4* q = static_cast<const uint4*>(v.base);
-      const uint4 A = q[(uint32_t)ea], B = q[(uint32_t)eb];
+      const uint4 A = volume_word<uint4>(v, e.a), B = volume_word<uint4>(v, e.b);
       w[0] = A.x; w[1] = A.y; w[2] = A.z; w[3] = A.w;
       w[4] = B.x; w[5] = B.y; w[6] = B.z; w[7] = B.w;
     } else {
-      const uint2* q = static_cast<const uint2*>(v.base);
-      const uint2 A = q[(uint32_t)ea], B = q[(uint32_t)eb];
+      const uint2 A = volume_word<uint2>(v, e.a), B = volume_word<uint2>(v, e.b);
       w[0] = A.x; w[1] = A.y; w[2] = B.x; w[3] = B.y;
     }
   }
@@ -292,17 +359,22 @@ struct BaseSampler<DT, LAYOUT_QUAD | kLayoutTab> : QuadSampler<DT, true> {};
 template <int DT, bool TAB>
 struct OctSampler {
   static constexpr int kWords = DT == DT_F32 ? 8 : 4;
-  __device__ static __forceinline__ void load(const DevVolume& v, int kx, int ky, int kz, bool live,
-                                              uint32_t (&w)[kWords]) {
-    const int ie = packed_entry<TAB>(v, kx, ky, kz + 1);
-    const int e = live ? ie : 0;
+  struct Addr {
+    entry_off_t<TAB> e;   // byte offset of the footprint's entry
+  };
+  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz,
+                                              bool live) {
+    const entry_off_t<TAB> ie = packed_entry<TAB>(v, kx, ky, kz + 1);
+    return {live ? ie : 0u};
+  }
+  __device__ static __forceinline__ void fetch(const DevVolume& v, const Addr& a,
+                                               uint32_t (&w)[kWords]) {
     if constexpr (DT == DT_F32) {
-      const uint4* q = static_cast<const uint4*>(v.base) + 2 * (size_t)(uint32_t)e;
-      const uint4 A = q[0], B = q[1];
+      const uint4 A = volume_word<uint4>(v, a.e), B = volume_word<uint4>(v, a.e + 16u);
       w[0] = A.x; w[1] = A.y; w[2] = A.z; w[3] = A.w;
       w[4] = B.x; w[5] = B.y; w[6] = B.z; w[7] = B.w;
     } else {
-      const uint4 Q = static_cast<const uint4*>(v.base)[(uint32_t)e];
+      const uint4 Q = volume_word<uint4>(v, a.e);
       w[0] = Q.x; w[1] = Q.y; w[2] = Q.z; w[3] = Q.w;
     }
   }
@@ -320,39 +392,67 @@ struct BaseSampler<DT, LAYOUT_OCT> : OctSampler<DT, false> {};
 template <int DT>
 struct BaseSampler<DT, LAYOUT_OCT | kLayoutTab> : OctSampler<DT, true> {};
 
-// Trilinear lookup of the base volume at continuous texel coordinates f.
+// A base-volume trilinear lookup at continuous texel coordinates f, in three
+// phases: prepare (corner, weights, occupancy, entry addresses), fetch, and
+// finish (the lerps).
+template <int DT, int LAYOUT>
+struct BaseLookup {
+  using S = BaseSampler<DT, LAYOUT>;
+  typename S::Addr addr;
+  float wx, wy, wz;
+  bool live;   // false: an empty brick, the lookup is exactly 0
+
+  __device__ static __forceinline__ BaseLookup prepare(const DevVolume& v, float fx, float fy,
+                                                       float fz) {
+    BaseLookup q;
+    int kx, ky, kz;
+    split_coord(fx, v.nx, q.wx, kx);
+    split_coord(fy, v.ny, q.wy, ky);
+    split_coord(fz, v.nz, q.wz, kz);
+    q.live = occupied(v, kx, ky, kz);
+    q.addr = S::addr(v, kx, ky, kz, q.live);
+    return q;
+  }
+
+  __device__ __forceinline__ void fetch(const DevVolume& v, uint32_t (&w)[S::kWords]) const {
+    S::fetch(v, addr, w);
+  }
+
+  __device__ __forceinline__ float finish(const uint32_t (&w)[S::kWords]) const {
+    if constexpr (DT == DT_F16) {
+      // the four x-lerps as 16-bit dot products accumulated in float32:
+      // a + w (b - a) = dot((a, b), (-w, w)) + a, with w rounded to half
+      uint32_t p[4];
+      S::pairs(w, p);
+      float c[4];
+      const half2_t wt = {(_Float16)(-wx), (_Float16)wx};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const half2_t h = __builtin_bit_cast(half2_t, p[k]);
+        c[k] = __builtin_amdgcn_fdot2(h, wt, (float)h.x, false);
+      }
+      const float c0 = lerp(c[0], c[1], wy), c1 = lerp(c[2], c[3], wy);
+      return live ? lerp(c0, c1, wz) : 0.0f;
+    } else {
+      float c[8];
+      S::decode(w, c);
+      const float c0 = lerp(lerp(c[0], c[1], wx), lerp(c[2], c[3], wx), wy);
+      const float c1 = lerp(lerp(c[4], c[5], wx), lerp(c[6], c[7], wx), wy);
+      return live ? lerp(c0, c1, wz) : 0.0f;
+    }
+  }
+};
+
+// Trilinear lookup of the base volume at continuous texel coordinates f. A
+// lookup in an empty brick keeps its fetch, pointed at entry 0 (a line every
+// wavefront shares), so that the light march's fetches stay in flight
+// together, and is 0.
 template <int DT, int LAYOUT>
 __device__ __forceinline__ float base_lookup(const DevVolume& v, float fx, float fy, float fz) {
-  using S = BaseSampler<DT, LAYOUT>;
-  float wx, wy, wz;
-  int kx, ky, kz;
-  split_coord(fx, v.nx, wx, kx);
-  split_coord(fy, v.ny, wy, ky);
-  split_coord(fz, v.nz, wz, kz);
-  const bool live = occupied(v, kx, ky, kz);
-  uint32_t w[S::kWords];
-  S::load(v, kx, ky, kz, live, w);
-  if constexpr (DT == DT_F16) {
-    // the four x-lerps as 16-bit dot products accumulated in float32:
-    // a + w (b - a) = dot((a, b), (-w, w)) + a, with w rounded to half
-    uint32_t p[4];
-    S::pairs(w, p);
-    float c[4];
-    const half2_t wt = {(_Float16)(-wx), (_Float16)wx};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const half2_t h = __builtin_bit_cast(half2_t, p[k]);
-      c[k] = __builtin_amdgcn_fdot2(h, wt, (float)h.x, false);
-    }
-    const float c0 = lerp(c[0], c[1], wy), c1 = lerp(c[2], c[3], wy);
-    return live ? lerp(c0, c1, wz) : 0.0f;
-  } else {
-    float c[8];
-    S::decode(w, c);
-    const float c0 = lerp(lerp(c[0], c[1], wx), lerp(c[2], c[3], wx), wy);
-    const float c1 = lerp(lerp(c[4], c[5], wx), lerp(c[6], c[7], wx), wy);
-    return live ? lerp(c0, c1, wz) : 0.0f;
-  }
+  const BaseLookup<DT, LAYOUT> q = BaseLookup<DT, LAYOUT>::prepare(v, fx, fy, fz);
+  uint32_t w[BaseSampler<DT, LAYOUT>::kWords];
+  q.fetch(v, w);
+  return q.finish(w);
 }
 
 // Index k of a periodic axis of n texels, wrapped into [0, n).

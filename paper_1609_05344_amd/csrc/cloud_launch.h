@@ -22,9 +22,9 @@ struct Tuning {
 Tuning& tuning();
 
 // Layout argument of the sampling kernels for a volume: a packed layout whose
-// volume fits the LDS entry-index tables (tab_fits) carries kLayoutTab.
+// volume fits the LDS byte-offset tables (DevVolume::tab) carries kLayoutTab.
 inline int sampler_layout(const DevVolume& v, int layout) {
-  return layout != LAYOUT_DENSE && tab_fits(v.nx, v.ny, v.nz) ? layout | kLayoutTab : layout;
+  return layout != LAYOUT_DENSE && v.tab ? layout | kLayoutTab : layout;
 }
 
 // Render tile walk under the current

@@ -18,9 +18,10 @@ constexpr int kMaxViews = 16;   // cameras carried by value in one launch
 enum { LAYOUT_DENSE = 0, LAYOUT_QUAD = 1, LAYOUT_OCT = 2 };
 
 // A packed entry index is the sum of a term of x, a term of y and a term of
-// z (see packed_index). For a volume of at most kTabAxis texels along x and
-// y and fewer along z, the kernels stage those terms in LDS tables and index
-// through them; the sampler's layout argument then carries kLayoutTab.
+// z (see packed_index), and so is its byte offset. For a volume of at most
+// kTabAxis texels along x and y, fewer along z, and below 4 GiB stored, the
+// kernels stage those byte-offset terms in LDS tables and index through them;
+// the sampler's layout argument then carries kLayoutTab.
 constexpr int kLayoutTab = 4;
 constexpr int kTabAxis = 1024;
 inline __host__ __device__ bool tab_fits(int nx, int ny, int nz) {
@@ -71,6 +72,9 @@ struct DevVolume {
   int plane;            // dense: nx * ny; packed: the plane stride of packed_index
   int row;              // dense: nx; packed: the row stride of packed_index
   int bx, by, bz;       // packed: brick shifts of packed_index
+  int entry_shift;      // packed: log2 of an entry's bytes (quad 4, oct 8 texels)
+  int tab;              // packed and indexed through the LDS byte-offset tables
+  uint32_t tab_bytes;   // with tab: the stored bytes (the buffer range of its fetches)
   // continuous texel coordinate along each axis: f = p * s + o, texel k's
   // centre at f = k (texel centres at box_min + (k + 0.5) * extent / n)
   float sx, sy, sz, ox, oy, oz;

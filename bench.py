@@ -619,6 +619,7 @@ def quality_report(cf, scenes, torch) -> dict:
       steps): max and p99 abs RGBA error over 20000 seeded pixels of the FP32,
       FP16 and BF16 storage paths against the FP64 oracle on the decoded stored
       volume, and of the 16-bit paths against the oracle on the FP32 volume;
+      the same against the FP32 source at H (quad layout, occupancy);
     * 8 jittered steps + TAA against the 128-step unjittered render (C2, 720p):
       the same camera after a 16-frame accumulation at a fixed camera, next to
       one 8-step frame with and without jitter."""
@@ -649,6 +650,22 @@ def quality_report(cf, scenes, torch) -> dict:
                     "max_vs_oracle_on_f32_source": float(e_src.max()),
                     "p99_vs_oracle_on_f32_source": float(np.percentile(e_src, 99))}
     out["precision_C3"] = prec
+    # the headline workload's 16-bit forms (quad layout, occupancy) against the
+    # oracle on the FP32 source, orbit frame 400
+    wh = scenes.workload("H")
+    pixh = scenes.random_pixels(wh.width, wh.height, 20000, seed=98)
+    srch = scenes.make_scene(wh, dtype="f32")
+    refh = O.render(ovol(srch), wh.camera(400), wh.params, wh.width, wh.height, frame=400,
+                    pixels=pixh)
+    prec_h = {}
+    for dt in ("f32", "f16", "bf16"):
+        vol = cf.device_volume(scenes.make_scene(wh, dtype=dt), layout="quad", occupancy=True)
+        img = cf.cloud_render(vol, wh.camera(400), wh.params, 400, wh.width,
+                              wh.height).cpu().numpy()
+        e = np.abs(img[pixh[:, 1], pixh[:, 0]].astype(np.float64) - refh)
+        prec_h[dt] = {"max_vs_oracle_on_f32_source": float(e.max()),
+                      "p99_vs_oracle_on_f32_source": float(np.percentile(e, 99))}
+    out["precision_H"] = prec_h
 
     w2 = scenes.workload("C2")
     vol = cf.device_volume(scenes.make_scene(w2), layout="quad", occupancy=True)

@@ -41,8 +41,8 @@ extern "C" {
 #endif
 
 /* Raised whenever a struct layout or a signature changes (2: brick_log2 in
- * cloud_volume, queues in cloud_serve_config, depth/trace/ceiling/composite
- * entry points). */
+ * cloud_volume, queues in cloud_serve_config, depth/trace/composite entry
+ * points; 3: the gather record and replay entry points). */
 #define CLOUD_ABI_VERSION 3
 
 enum {
@@ -309,7 +309,7 @@ int cloud_gather_record(const cloud_volume* volume, const cloud_camera* cameras,
                         const uint32_t* trace, int32_t max_slots, uint32_t* codes,
                         uint32_t* slot_counts, void* hip_stream);
 
-/* Measurement only: the gather ceiling of a recorded pattern. One launch on
+/* Measurement only: the fetch-only replay of a recorded pattern. One launch on
  * the render's launch shape and tile walk; each wavefront takes its slots in
  * order and fetches the volume words of each lane's corner (the entry index
  * of the volume's layout; entry 0 for a redirected corner), with no camera,

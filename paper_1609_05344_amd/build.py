@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_NAME = "libcloud.so"
 LIB_PATH = os.path.join(PKG, LIB_NAME)
 
-SOURCES = ["render.hip", "taa.hip", "ceiling.hip", "composite.hip", "api.cpp", "serve.hip", "serve_core.cpp"]
+SOURCES = ["render.hip", "taa.hip", "gather.hip", "composite.hip", "api.cpp", "serve.hip", "serve_core.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -63,7 +63,7 @@ hipError_t launch_taa_reproject(const float* cur, const float* depth, const floa
 // recorded in trace; random == true: as many lookups per pixel at uniformly
 // random footprints of the volume) into out [n_views][H][W][4].
 // Record the render's lookups of n_views (<= kMaxViews) views as corner
-// codes per wavefront slot, and replay recorded codes (see ceiling.hip).
+// codes per wavefront slot, and replay recorded codes (see gather.hip).
 hipError_t launch_gather_record(const DevVolume& v, int layout, const DevParams& p,
                                 const DevCameras& c, int n_views, uint32_t frame, int W, int H,
                                 const uint32_t* trace, int max_slots, uint32_t* codes,

@@ -1,7 +1,7 @@
-// Gather ceiling: the render's own density fetches replayed without the
-// arithmetic around them, to measure what the memory system allows for the
-// render's access pattern (the per-pixel jitter's cost is cache misses,
-// Sections 4 and 5).
+// Gather record and replay: the render's own density fetches replayed
+// without the arithmetic around them, a measurement of the render's access
+// pattern on its own (the per-pixel jitter's cost is cache misses, Sections 4
+// and 5).
 //
 // Two kernels. gather_record_kernel walks the render's rays once (untimed)
 // and writes every lookup the render makes as the texel corner of its

@@ -494,12 +494,16 @@ def plain_on_stream_cameras(cf, scenes, torch, np, w, vol, p, n_streams: int, ro
 
 def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams: int,
                        seconds: float, warm_s: float = 0.5, queues: int = 1,
-                       graphs: bool = True) -> dict:
-    """n_streams streams of the workload, each submitting its next frame as
-    soon as the previous one completes; frames/s and frame latency
-    (submit -> done) over the measured window. A multi-view workload gives
-    stream s the camera of view s (mod the view count). graphs=False makes the
-    server launch its kernels one by one instead of replaying captured graphs."""
+                       graphs: bool = True, window: int = 1, history_in_output: bool = True,
+                       start_lead_us: int = 0) -> dict:
+    """n_streams streams of the workload, each keeping `window` frames in
+    flight: it submits its next frame as soon as one completes. Frames/s and
+    frame latency (submit -> done) over the measured window. A multi-view
+    workload gives stream s the camera of view s (mod the view count).
+    graphs=False makes the server launch its kernels one by one instead of
+    replaying captured graphs; history_in_output has each stream resolve
+    against its previous frame's output (one output buffer a stream, resolved
+    in place) instead of a library copy of the history."""
     import numpy as np
     sc = scenes.make_scene(w, dtype=dtype)
     vol = cf.device_volume(sc, layout=layout, occupancy=True)
@@ -512,10 +516,13 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
         return stream_camera(scenes, w, s, n_streams, f)
 
     with cf.Server(vol, budget_bytes=n_streams * W * H * 40, max_batch=64, queues=queues,
-                   use_graphs=graphs) as srv:
+                   use_graphs=graphs, history_in_output=history_in_output,
+                   start_lead_us=start_lead_us) as srv:
         t_start = time.monotonic()
         for s in range(n_streams):
-            srv.submit(s, camera(s, 0), w.params, W, H, 0, outs[s])
+            for _ in range(window):
+                srv.submit(s, camera(s, frame[s]), w.params, W, H, frame[s], outs[s])
+                frame[s] += 1
         t_end = t_start + warm_s + seconds
         while time.monotonic() < t_end:
             got = srv.poll(256)
@@ -528,17 +535,21 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
                 if c["t_done_ns"] * 1e-9 >= t_start + warm_s:
                     lat.append((c["t_done_ns"] - c["t_submit_ns"]) * 1e-6)
                     done_t.append(c["t_done_ns"] * 1e-9)
-                frame[s] += 1
                 srv.submit(s, camera(s, frame[s]), w.params, W, H, frame[s], outs[s])
+                frame[s] += 1
         st = srv.stats()
     done_t.sort()
     span = done_t[-1] - done_t[0] if len(done_t) > 1 else float("nan")
     fps = (len(done_t) - 1) / span if len(done_t) > 1 else 0.0
     return {"form": f"served, {dtype} storage, {layout} layout", "streams": n_streams,
+            "frames_in_flight_per_stream": window,
+            "history": "previous output" if history_in_output else "library copy",
             "frames_per_s": round(fps, 1), "ms_per_frame": round(1e3 / fps, 4) if fps else None,
             "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
             "latency_p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "frames": len(lat), "batches": st["batches"], "queues": queues, "graphs": graphs}
+            "frames": len(lat), "batches": st["batches"],
+            "frames_per_batch": round(st["completed"] / max(st["batches"], 1), 2),
+            "queues": queues, "graphs": graphs, "start_lead_us": start_lead_us}
 
 
 def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: float = 1.0,
@@ -548,7 +559,9 @@ def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: fl
     resolution from {640x360, 1280x720, 1920x1080, 3840x2160} and a step
     count from {8, 16, 32, 128} drawn once; Poisson arrivals at rate_hz in
     total, each for a uniformly chosen stream; a shared FP16 256^3 volume.
-    Latency runs from the scheduled arrival to completion."""
+    Each stream renders into a ring of output buffers and resolves against
+    its previous output. Latency runs from the scheduled arrival to
+    completion."""
     import numpy as np
     from dataclasses import replace
     rng = np.random.default_rng(seed)
@@ -569,7 +582,7 @@ def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: fl
     gaps = rng.exponential(1.0 / rate_hz, size=int(rate_hz * (warm_s + seconds) * 1.5) + 16)
     which = rng.integers(n_streams, size=gaps.size)
     with cf.Server(vol, budget_bytes=budget_bytes, max_batch=64, max_queue=4096,
-                   queues=queues) as srv:
+                   queues=queues, history_in_output=True) as srv:
         t0 = time.monotonic()
         t_arr = t0 + np.cumsum(gaps)
         k, t_end = 0, t0 + warm_s + seconds
@@ -749,6 +762,19 @@ def main():
     ap.add_argument("--no-replay", action="store_true",
                     help="skip the offset-replay measurement")
     ap.add_argument("--serve-queues", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--served-window", type=int, default=0, choices=[0, 1, 2],
+                    help="frames each closed-loop stream keeps in flight (0: 2 for fewer than "
+                         "16 streams, else 1)")
+    ap.add_argument("--served-history", default="output", choices=["output", "library"],
+                    help="served streams resolve against their previous output, or against "
+                         "a library copy of the history")
+    ap.add_argument("--serve-blocks-per-cu", type=int, default=0,
+                    help="cap on the persistent serving render's workgroups per CU in the "
+                         "closed-loop served leg (0: as many as fit; the open-loop mix always "
+                         "runs uncapped)")
+    ap.add_argument("--serve-lead-us", type=int, default=0,
+                    help="batch start lead of the server (0: its default; -1: start each "
+                         "batch as soon as a slot is free)")
     ap.add_argument("--serve-graphs", type=int, default=1, choices=[0, 1],
                     help="served leg: 1 replays captured graphs, 0 launches kernels one by one")
     ap.add_argument("--no-occupancy", action="store_true",
@@ -966,9 +992,13 @@ def main():
                        if w.views == 1 and not w.display else None)
         del cur, hist, vol
         torch.cuda.empty_cache()
+        window = args.served_window or (2 if n_streams < 16 else 1)
+        cf.cloud_tune("serve_blocks_per_cu", args.serve_blocks_per_cu)
         served = served_closed_loop(cf, scenes, torch, w, args.served_dtype, args.served_layout,
                                     n_streams, args.served_seconds, queues=args.serve_queues,
-                                    graphs=args.serve_graphs == 1)
+                                    graphs=args.serve_graphs == 1, window=window,
+                                    history_in_output=args.served_history == "output",
+                                    start_lead_us=args.serve_lead_us)
         # a plain step renders and resolves every view once; on the served
         # leg's own cameras where they differ from the timed window's
         served["plain_frames_per_s"] = plain_views or round(V * 1e3 / ms_per_step, 1)
@@ -976,11 +1006,13 @@ def main():
                                 f"{n_streams} stream cameras" if plain_views else
                                 "the timed plain step")
         served["speedup_vs_plain"] = round(served["frames_per_s"] / served["plain_frames_per_s"], 3)
+        served["serve_blocks_per_cu"] = args.serve_blocks_per_cu
         line["served"] = served
     if not args.no_served and not args.no_c4:
         # the serving form's latency metric: 64 streams of mixed resolutions and
         # step counts, open-loop Poisson arrivals at the specified total rate,
         # and at half of it
+        cf.cloud_tune("serve_blocks_per_cu", 0)
         line["served_c4"] = {
             "workload": "64 streams, resolutions in {640x360,1280x720,1920x1080,3840x2160}, "
                         "steps in {8,16,32,128}, shared f16 256^3 (oct layout, occupancy), TAA "

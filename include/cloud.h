@@ -42,8 +42,9 @@ extern "C" {
 
 /* Raised whenever a struct layout or a signature changes (2: brick_log2 in
  * cloud_volume, queues in cloud_serve_config, depth/trace/composite entry
- * points; 3: the gather record and replay entry points). */
-#define CLOUD_ABI_VERSION 3
+ * points; 3: the gather record and replay entry points; 4: history_in_output
+ * and start_lead_us in cloud_serve_config). */
+#define CLOUD_ABI_VERSION 4
 
 enum {
   CLOUD_OK = 0,
@@ -370,7 +371,10 @@ int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t ds
  *      pixels (each tile holds 256 pixels).
  *  "render_blocks_per_cu" (0..64, default 0 = no cap) -- at most this many
  *      render workgroups resident per CU, enforced by reserving LDS at
- *      launch (CLOUD_E_INVALID when the device's LDS cannot express it). */
+ *      launch (CLOUD_E_INVALID when the device's LDS cannot express it).
+ *  "serve_blocks_per_cu" (0..64, default 0 = as many as fit) -- the
+ *      persistent serving render's workgroups per CU, read by
+ *      cloud_serve_create. */
 int cloud_tune(const char* key, int32_t value);
 
 /* Checks that [ptr, ptr + bytes) lies inside one HIP device allocation: the
@@ -398,18 +402,24 @@ int cloud_jitter_offsets(const uint32_t* pixel_xy, int64_t n, uint32_t frame_ind
  * into batches as batch slots and device memory allow, and runs each batch as
  * one persistent render launch plus one batched resolve launch (replayed from
  * a captured HIP graph). Up to two batches are in flight, so requests that
- * arrive while the device works are admitted into the next batch. A stream has
- * at most one request in flight (its frames chain through the history);
- * requests of different streams overlap. Results are bitwise identical to
- * cloud_render followed by cloud_taa_resolve on the same inputs, whatever
- * else is in the batch.
+ * arrive while the device works are admitted into the next batch; with a
+ * batch in flight, the next one starts shortly before the work ahead of it is
+ * expected to end (start_lead_us), and admits arrivals until then. A stream's
+ * frames run in submission order, one per batch (they chain through the
+ * history), and a stream may have two requests in flight, in consecutive
+ * batches. Requests of different streams overlap.
+ * Results are bitwise identical to cloud_render followed by cloud_taa_resolve
+ * on the same inputs, whatever else is in the batch. A request that resolves
+ * against the history of a failed request fails too.
  *
- * Stream state (the history plus a scratch frame, 2 x width x height x 16
- * bytes) is library-owned: allocated when the stream's first request is
- * admitted, counted against hbm_budget_bytes, freed by
- * cloud_serve_close_stream or cloud_serve_destroy. A stream's resolution is
- * fixed by its first request. frame_index 0 (or a stream without valid
- * history) copies the rendered frame instead of resolving it.
+ * Stream state is library-owned: a scratch frame (two with queues = 2),
+ * plus, unless history_in_output is set, the history (width x height x 16
+ * bytes each, each rounded up to 256 bytes). It
+ * is allocated when the stream's first request is admitted, counted against
+ * hbm_budget_bytes, and freed by cloud_serve_close_stream or
+ * cloud_serve_destroy. A stream's resolution is fixed by its first request.
+ * frame_index 0 (or a stream without valid history) copies the rendered frame
+ * instead of resolving it.
  *
  * Thread safety: submit, poll, wait and stats may be called from any thread
  * concurrently; create, close_stream and destroy must not race with other
@@ -425,9 +435,25 @@ typedef struct {
   int32_t device;             /* HIP device ordinal */
   float taa_blend;            /* resolve blend, (0, 1] */
   int32_t use_graphs;         /* 1: replay captured graphs; 0: plain launches */
-  int32_t queues;             /* HIP streams batches alternate over: 1 (0 means
-                               * 1) keeps batches in order on one queue; 2 lets
-                               * a batch start while the previous one drains */
+  int32_t queues;             /* 1 (0 means 1): a batch's table copy, render
+                               * and resolve run in order on one HIP stream; 2:
+                               * resolves run on a second stream, each after
+                               * its batch's render and the previous resolve,
+                               * overlapping the next batch's render (stream
+                               * state then holds two scratch frames) */
+  int32_t history_in_output;  /* 1: a stream's history is its previous frame's
+                               * output buffer, not a library copy: each
+                               * resolved pixel is written once, and the caller
+                               * leaves a frame's output unmodified until the
+                               * stream's next frame has completed (one buffer
+                               * for every frame of a stream is allowed; it is
+                               * then resolved in place). 0: the library keeps
+                               * the history. */
+  int32_t start_lead_us;      /* with a batch in flight, the next starts when
+                               * the work ahead is expected to end within this
+                               * many microseconds plus an eighth of that work;
+                               * 0: the default (300); -1: as soon as a slot is
+                               * free */
 } cloud_serve_config;
 
 typedef struct {
@@ -449,7 +475,8 @@ int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg
 
 /* Queues one frame of stream stream_id. out_rgba: device [height][width][4]
  * float32, caller-owned, 16-byte aligned, not touched by the caller until
- * the request completes. Returns CLOUD_E_BUSY when the queue is full (retry
+ * the request completes (with history_in_output, until the stream's next
+ * request completes; it may be read). Returns CLOUD_E_BUSY when the queue is full (retry
  * later), CLOUD_E_NOMEM when this stream's state can never fit the budget,
  * CLOUD_E_INVALID for bad arguments or a resolution that differs from the
  * stream's first request. Camera and params are copied. */

@@ -59,7 +59,7 @@ class cloud_params(ctypes.Structure):
 _lib = None
 
 
-ABI_VERSION = 3   # the struct layouts and signatures this binding marshals
+ABI_VERSION = 4   # the struct layouts and signatures this binding marshals
 
 
 def load():
@@ -493,7 +493,7 @@ def cloud_taa_resolve(current, history, out, blend: float, frame_index: int, str
 class cloud_serve_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", c_uint64), ("max_batch", c_int32), ("max_queue", c_int32),
                 ("device", c_int32), ("taa_blend", c_float), ("use_graphs", c_int32),
-                ("queues", c_int32)]
+                ("queues", c_int32), ("history_in_output", c_int32), ("start_lead_us", c_int32)]
 
 
 class cloud_serve_stats_t(ctypes.Structure):
@@ -533,11 +533,13 @@ class Server:
 
     def __init__(self, volume: Volume, budget_bytes: int = 64 << 30, max_batch: int = 64,
                  max_queue: int = 1024, device: int = 0, taa_blend: float = 0.1,
-                 use_graphs: bool = True, queues: int = 1):
+                 use_graphs: bool = True, queues: int = 1, history_in_output: bool = False,
+                 start_lead_us: int = 0):
         self.lib = _bind_serve(load())
         self.volume = volume
         cfg = cloud_serve_config(int(budget_bytes), int(max_batch), int(max_queue), int(device),
-                                 float(taa_blend), 1 if use_graphs else 0, int(queues))
+                                 float(taa_blend), 1 if use_graphs else 0, int(queues),
+                                 1 if history_in_output else 0, int(start_lead_us))
         h = c_void_p()
         check(self.lib.cloud_serve_create(ctypes.byref(volume.struct), ctypes.byref(cfg),
                                           ctypes.byref(h)))

@@ -800,6 +800,11 @@ int cloud_tune(const char* key, int32_t value) {
     tuning().render_blocks_per_cu = value;
     return CLOUD_OK;
   }
+  if (k == "serve_blocks_per_cu") {
+    if (value < 0 || value > 64) return fail(CLOUD_E_INVALID, "serve_blocks_per_cu must be in [0, 64]");
+    tuning().serve_blocks_per_cu = value;
+    return CLOUD_OK;
+  }
   return fail(CLOUD_E_INVALID, "unknown tuning key " + k);
   CLOUD_GUARD_END
 }

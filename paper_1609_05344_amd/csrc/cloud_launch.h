@@ -18,6 +18,9 @@ struct Tuning {
   // cap on resident render workgroups per CU (0: none, the default; with the
   // bricked packed layouts every measured cap was slower)
   int render_blocks_per_cu = 0;
+  // cap on the persistent serving render's workgroups per CU, read when a
+  // server is created (0: as many as fit)
+  int serve_blocks_per_cu = 0;
 };
 Tuning& tuning();
 

@@ -106,7 +106,10 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol,
 // 128-byte lines) of every request, grid-strided. A request without usable
 // history copies its frame; otherwise the 3x3 neighbourhood clamp and blend
 // of the single-frame resolve, the tile and its one-pixel halo staged in LDS.
-// The result goes to the stream's history and to the caller's output.
+// The result goes to the caller's output and, where the library keeps the
+// stream's history, to that history too. The history read may be the output
+// itself (a stream that reuses one output buffer): each pixel's history is
+// read and written by the same thread.
 __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* __restrict__ tab) {
   constexpr int TW = kServeTaaW, TH = kServeTaaH;
   __shared__ float4 tile[TH + 2][TW + 2];
@@ -121,7 +124,8 @@ __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* __rest
     const int tyi = k / it.taa_tiles_x, txi = k - tyi * it.taa_tiles_x;
     const int bx = txi * TW, by = tyi * TH;
     const global_float4* cur = as_global(it.cur);
-    global_float4* hist = as_global(it.hist);
+    const global_float4* hist_in = as_global(const_cast<void*>(it.hist_in));
+    global_float4* hist_out = as_global(it.hist_out);
     global_float4* out = as_global(it.out);
     const int px = bx + lx, py = by + ly;
     const bool inside = px < W && py < H;
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* __rest
     if (it.reset) {
       if (inside) {
         const float4 v = cur[p];
-        hist[p] = v;
+        if (hist_out) hist_out[p] = v;
         out[p] = v;
       }
       continue;
@@ -153,14 +157,14 @@ __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* __rest
           hi.x = fmaxf(hi.x, v.x); hi.y = fmaxf(hi.y, v.y); hi.z = fmaxf(hi.z, v.z); hi.w = fmaxf(hi.w, v.w);
         }
       }
-      float4 h = hist[p];
+      float4 h = hist_in[p];
       h.x = fminf(fmaxf(h.x, lo.x), hi.x);
       h.y = fminf(fmaxf(h.y, lo.y), hi.y);
       h.z = fminf(fmaxf(h.z, lo.z), hi.z);
       h.w = fminf(fmaxf(h.w, lo.w), hi.w);
       const float4 r = make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
                                    fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w));
-      hist[p] = r;
+      if (hist_out) hist_out[p] = r;
       out[p] = r;
     }
     __syncthreads();
@@ -205,12 +209,23 @@ RenderFn pick(int dtype, int layout, bool detail) {
 }
 
 constexpr int kSlots = 2;
+// Batch start lead: enough for the table copy and graph launch to be queued
+// before the work ahead ends (the scheduler adds an eighth of that work).
+constexpr int kDefaultStartLeadUs = 300;
 
+// Batches run on one queue (queues = 1): table copy, persistent render and
+// batched resolve in order. With two queues the resolves run on the second:
+// a batch's resolve (memory-bound) waits for its render and for the previous
+// resolve, and overlaps the next batch's render (bound by the vector ALUs and
+// the texture path). A stream's consecutive requests may then be rendered
+// while the previous one is still being resolved, so each stream has two
+// scratch frames, used alternately.
 class HipExecutor : public serve::Executor {
  public:
   HipExecutor(int device, const DevVolume& v, int dtype, int layout, float blend, bool graphs,
-              int queues)
-      : device_(device), vol_(v), blend_(blend), graphs_(graphs), queues_(queues) {
+              int queues, bool history_in_output)
+      : device_(device), vol_(v), blend_(blend), graphs_(graphs), split_(queues == 2),
+        history_in_output_(history_in_output) {
     fn_ = pick(dtype, sampler_layout(v, layout), v.detail != nullptr);
   }
 
@@ -224,12 +239,16 @@ class HipExecutor : public serve::Executor {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn_),
                                                      256, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 4;
+    const int cap = tuning().serve_blocks_per_cu;
+    if (cap > 0) per_cu = std::min(per_cu, cap);
     render_blocks_ = cus * per_cu;
     taa_blocks_ = cus * 8;
-    for (int q = 0; q < queues_; ++q)
+    for (int q = 0; q < (split_ ? 2 : 1); ++q)
       if ((e = hipStreamCreateWithFlags(&stream_[q], hipStreamNonBlocking)) != hipSuccess) return err(e, msg);
     for (int s = 0; s < kSlots; ++s) {
       if ((e = hipEventCreateWithFlags(&event_[s], hipEventDisableTiming)) != hipSuccess) return err(e, msg);
+      if (split_ && (e = hipEventCreateWithFlags(&rendered_[s], hipEventDisableTiming)) != hipSuccess)
+        return err(e, msg);
       if ((e = hipHostMalloc(reinterpret_cast<void**>(&host_[s]), sizeof(ServeTable), hipHostMallocDefault)) != hipSuccess)
         return err(e, msg);
       std::memset(host_[s], 0, sizeof(ServeTable));
@@ -242,23 +261,37 @@ class HipExecutor : public serve::Executor {
 
   ~HipExecutor() override {
     (void)hipSetDevice(device_);
+    for (int q = 0; q < 2; ++q)
+      if (stream_[q]) (void)hipStreamSynchronize(stream_[q]);
     for (int s = 0; s < kSlots; ++s) {
-      if (stream_[s]) (void)hipStreamSynchronize(stream_[s]);
-    }
-    for (int s = 0; s < kSlots; ++s) {
-      if (exec_[s]) (void)hipGraphExecDestroy(exec_[s]);
-      if (graph_[s]) (void)hipGraphDestroy(graph_[s]);
+      for (int g = 0; g < 2; ++g) {
+        if (exec_[s][g]) (void)hipGraphExecDestroy(exec_[s][g]);
+        if (graph_[s][g]) (void)hipGraphDestroy(graph_[s][g]);
+      }
       if (dev_[s]) (void)hipFree(dev_[s]);
       if (host_[s]) (void)hipHostFree(host_[s]);
       if (event_[s]) (void)hipEventDestroy(event_[s]);
-      if (stream_[s]) (void)hipStreamDestroy(stream_[s]);
+      if (rendered_[s]) (void)hipEventDestroy(rendered_[s]);
     }
+    for (int q = 0; q < 2; ++q)
+      if (stream_[q]) (void)hipStreamDestroy(stream_[q]);
   }
 
   void thread_init() override { (void)hipSetDevice(device_); }
 
+  // Scratch frames (two with a resolve queue), plus the history unless it
+  // lives in the outputs.
   size_t stream_bytes(int w, int h) override {
-    return 2 * (((size_t)w * h * 16 + 255) & ~(size_t)255);
+    return (scratch_frames() + (history_in_output_ ? 0 : 1)) * frame_bytes(w, h);
+  }
+
+  // Device time of a request is roughly its samples: a primary step plus,
+  // where there is cloud, the light march's steps; the resolve is a few
+  // samples' worth a pixel.
+  double cost(const serve::Item& r) override {
+    Payload pl;
+    std::memcpy(&pl, r.payload.data(), sizeof pl);
+    return (double)r.width * r.height * (pl.prm.steps * (1.0 + 0.5 * pl.prm.light_steps) + 4.0);
   }
 
   int alloc(size_t bytes, void** mem) override {
@@ -287,9 +320,17 @@ class HipExecutor : public serve::Executor {
       taa_tile += it.taa_tiles_x * ((r.height + kServeTaaH - 1) / kServeTaaH);
       it.reset = r.reset_history ? 1 : 0;
       it.frame = r.frame;
-      const size_t half = stream_bytes(r.width, r.height) / 2;
-      it.cur = r.stream_mem;
-      it.hist = static_cast<char*>(r.stream_mem) + half;
+      char* mem = static_cast<char*>(r.stream_mem);
+      const size_t fb = frame_bytes(r.width, r.height);
+      it.cur = mem + (scratch_frames() == 2 ? (r.seq & 1) * fb : 0);
+      if (history_in_output_) {
+        // the history is the previous request's output
+        it.hist_in = r.reset_history ? nullptr : r.prev_out;
+        it.hist_out = nullptr;
+      } else {
+        it.hist_out = mem + scratch_frames() * fb;
+        it.hist_in = it.hist_out;
+      }
       it.out = r.out;
       tile += it.tiles_x * it.tiles_y;
     }
@@ -301,13 +342,16 @@ class HipExecutor : public serve::Executor {
     const TileWalk tw = tile_walk();
     t->supertile = tw.S;
     t->xcd_run = tw.L;
-    hipError_t e;
-    if (graphs_) {
-      e = hipGraphLaunch(exec_[slot], queue(slot));
-    } else {
-      e = enqueue(slot);
+    hipError_t e = graphs_ ? hipGraphLaunch(exec_[slot][0], stream_[0]) : enqueue_render(slot);
+    if (split_) {
+      // the resolve waits for this render (and, on its queue, for the
+      // previous resolve)
+      if (e == hipSuccess) e = hipEventRecord(rendered_[slot], stream_[0]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream_[1], rendered_[slot], 0);
+      if (e == hipSuccess)
+        e = graphs_ ? hipGraphLaunch(exec_[slot][1], stream_[1]) : enqueue_resolve(slot);
     }
-    if (e == hipSuccess) e = hipEventRecord(event_[slot], queue(slot));
+    if (e == hipSuccess) e = hipEventRecord(event_[slot], stream_[split_ ? 1 : 0]);
     return e == hipSuccess ? 0 : CLOUD_E_HIP;
   }
 
@@ -319,33 +363,43 @@ class HipExecutor : public serve::Executor {
   }
 
  private:
-  // Slots alternate over the queues. On one queue a batch's table copy is
-  // ordered after the previous batch; on two it can be issued while the
-  // previous persistent render still holds every CU and then waits for one.
-  hipStream_t queue(int slot) const { return stream_[slot % queues_]; }
+  static size_t frame_bytes(int w, int h) { return ((size_t)w * h * 16 + 255) & ~(size_t)255; }
+  size_t scratch_frames() const { return split_ ? 2 : 1; }
 
-  hipError_t enqueue(int slot) {
-    // table (with zeroed counters) -> persistent render -> batched resolve
-    const hipStream_t q = queue(slot);
+  // table (with zeroed counters) -> persistent render [-> batched resolve,
+  // on the same queue without a resolve queue]
+  hipError_t enqueue_render(int slot) {
+    const hipStream_t q = stream_[0];
     hipError_t e = hipMemcpyAsync(dev_[slot], host_[slot], sizeof(ServeTable),
                                   hipMemcpyHostToDevice, q);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn_, dim3(render_blocks_), dim3(256), 0, q, vol_, dev_[slot]->counters,
                        static_cast<const ServeTable*>(dev_[slot]));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(serve_taa_kernel, dim3(taa_blocks_), dim3(256), 0, q, dev_[slot]);
+    return split_ ? hipSuccess : enqueue_resolve(slot);
+  }
+
+  hipError_t enqueue_resolve(int slot) {
+    hipLaunchKernelGGL(serve_taa_kernel, dim3(taa_blocks_), dim3(256), 0, stream_[split_ ? 1 : 0],
+                       dev_[slot]);
     return hipGetLastError();
   }
 
+  // Graph g of slot: 0 the render (with the resolve on one queue), 1 the
+  // resolve on the resolve queue.
   hipError_t capture(int slot) {
-    const hipStream_t q = queue(slot);
-    hipError_t e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
-    const hipError_t le = enqueue(slot);
-    e = hipStreamEndCapture(q, &graph_[slot]);
-    if (le != hipSuccess) return le;
-    if (e != hipSuccess) return e;
-    return hipGraphInstantiate(&exec_[slot], graph_[slot], nullptr, nullptr, 0);
+    for (int g = 0; g < (split_ ? 2 : 1); ++g) {
+      const hipStream_t q = stream_[g];
+      hipError_t e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return e;
+      const hipError_t le = g == 0 ? enqueue_render(slot) : enqueue_resolve(slot);
+      e = hipStreamEndCapture(q, &graph_[slot][g]);
+      if (le != hipSuccess) return le;
+      if (e != hipSuccess) return e;
+      if ((e = hipGraphInstantiate(&exec_[slot][g], graph_[slot][g], nullptr, nullptr, 0)) != hipSuccess)
+        return e;
+    }
+    return hipSuccess;
   }
 
   static int err(hipError_t e, std::string* msg) {
@@ -357,15 +411,17 @@ class HipExecutor : public serve::Executor {
   DevVolume vol_;
   float blend_;
   bool graphs_;
-  int queues_;
+  bool split_;
+  bool history_in_output_;
   RenderFn fn_ = nullptr;
   int render_blocks_ = 0, taa_blocks_ = 0;
-  hipStream_t stream_[kSlots] = {};
-  hipEvent_t event_[kSlots] = {};
+  hipStream_t stream_[2] = {};        // render (and resolve) queue; resolve queue
+  hipEvent_t event_[kSlots] = {};     // batch done
+  hipEvent_t rendered_[kSlots] = {};  // batch rendered (resolve queue only)
   ServeTable* host_[kSlots] = {};
   ServeTable* dev_[kSlots] = {};
-  hipGraph_t graph_[kSlots] = {};
-  hipGraphExec_t exec_[kSlots] = {};
+  hipGraph_t graph_[kSlots][2] = {};
+  hipGraphExec_t exec_[kSlots][2] = {};
 };
 
 }  // namespace
@@ -395,7 +451,11 @@ int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg
     if (cfg->max_batch < 1 || cfg->max_batch > kMaxBatch)
       return fail(CLOUD_E_INVALID, "max_batch must be in [1, 64]");
     if (cfg->max_queue < 1) return fail(CLOUD_E_INVALID, "max_queue must be >= 1");
-    if (cfg->queues < 0 || cfg->queues > kSlots) return fail(CLOUD_E_INVALID, "queues must be 0, 1 or 2");
+    if (cfg->queues < 0 || cfg->queues > 2) return fail(CLOUD_E_INVALID, "queues must be 0, 1 or 2");
+    if (cfg->history_in_output != 0 && cfg->history_in_output != 1)
+      return fail(CLOUD_E_INVALID, "history_in_output must be 0 or 1");
+    if (cfg->start_lead_us < -1 || cfg->start_lead_us > 1000000)
+      return fail(CLOUD_E_INVALID, "start_lead_us must be in [-1, 1000000]");
     if (!std::isfinite(cfg->taa_blend) || !(cfg->taa_blend > 0.0f) || cfg->taa_blend > 1.0f)
       return fail(CLOUD_E_INVALID, "taa_blend must be in (0, 1]");
     int ndev = 0;
@@ -407,8 +467,10 @@ int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg
     if ((rc = prepare_volume(shared, &v, &dtype))) return rc;
     auto srv = std::make_unique<cloud_server>();
     srv->volume = *shared;
+    const int queues = cfg->queues == 0 ? 1 : cfg->queues;
     srv->ex = std::make_unique<HipExecutor>(cfg->device, v, dtype, shared->layout, cfg->taa_blend,
-                                            cfg->use_graphs != 0, cfg->queues == 0 ? 1 : cfg->queues);
+                                            cfg->use_graphs != 0, queues,
+                                            cfg->history_in_output != 0);
     std::string msg;
     if ((rc = srv->ex->init(&msg))) return fail(rc, msg);
     serve::Config sc;
@@ -416,6 +478,12 @@ int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg
     sc.max_batch = cfg->max_batch;
     sc.max_queue = cfg->max_queue;
     sc.depth = kSlots;
+    // renders run in launch order, and so do resolves, each after its
+    // batch's render: a stream's next request may follow its previous one in
+    // the next batch
+    sc.pipeline = kSlots;
+    sc.lead_ns = cfg->start_lead_us < 0 ? -1
+                 : 1000LL * (cfg->start_lead_us == 0 ? kDefaultStartLeadUs : cfg->start_lead_us);
     srv->sched = std::make_unique<serve::Scheduler>(srv->ex.get(), sc);
     *out = srv.release();
     return CLOUD_OK;

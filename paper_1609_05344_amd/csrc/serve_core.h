@@ -7,13 +7,22 @@
 //
 // Model. A request renders one frame of one stream and resolves it against
 // that stream's history (the temporal accumulation of jittered frames). A
-// stream's frames depend on each other through the history, so a stream has
-// at most one request in flight; requests of different streams are
+// stream's frames depend on each other through the history, so they run in
+// submission order, at most one per batch; requests of different streams are
 // independent and are batched together. Up to `depth` batches are in flight
-// at once: while the device works on one batch, newly arrived requests are
-// admitted into the next as memory and slots allow. A stream's state (history
-// plus a scratch frame) is allocated when its first request is admitted,
+// at once. When the executor runs batches in launch order, a stream may have
+// up to `pipeline` requests in flight, in consecutive batches (each batch's
+// resolve then finishes before the next one reads that history); otherwise
+// one. A stream's state is allocated when its first request is admitted,
 // counted against the budget, and freed when the stream is closed.
+//
+// Batch start. With nothing in flight a batch starts at once. With a batch
+// in flight, the next one would only wait behind it on the device, so it
+// keeps admitting arrivals until the work ahead of it is expected to end
+// within the start lead (lead_ns plus an eighth of that work), or until it
+// has a full batch's worth of requests queued. The expected end comes from
+// the executor's cost of each request and a running average of device time
+// per unit cost over finished batches.
 #pragma once
 
 #include <stddef.h>
@@ -49,8 +58,10 @@ struct Item {
   uint64_t request_id, stream_id;
   int width, height;
   uint32_t frame;
+  uint64_t seq;             // the stream's requests admitted before this one
   bool reset_history;       // frame 0, or no valid history yet
   void* out;                // caller's output buffer
+  void* prev_out;           // output buffer of the stream's previous request (or null)
   void* stream_mem;         // the stream's state allocation
   std::vector<unsigned char> payload;   // executor-specific request data
 };
@@ -68,6 +79,8 @@ class Executor {
   virtual int query(int slot) = 0;
   // Called on the scheduler thread before anything else.
   virtual void thread_init() {}
+  // Relative device cost of a request (any unit, the same for all requests).
+  virtual double cost(const Item& it) { return (double)it.width * it.height; }
 };
 
 struct Config {
@@ -75,6 +88,8 @@ struct Config {
   int max_batch = 64;          // requests per batch
   int max_queue = 1024;        // queued (not yet admitted) requests
   int depth = 2;               // batches in flight
+  int pipeline = 1;            // requests of one stream in flight (> 1: batches run in order)
+  int64_t lead_ns = -1;        // batch start lead; < 0: start as soon as a slot is free
   int poll_us = 20;            // scheduler wake-up period while batches run
 };
 
@@ -99,7 +114,11 @@ class Scheduler {
     int width = 0, height = 0;
     void* mem = nullptr;
     size_t bytes = 0;
-    bool busy = false, closing = false, history_valid = false;
+    int inflight = 0;           // requests in flight
+    uint64_t admitted = 0;      // requests admitted so far
+    bool closing = false, history_valid = false;
+    bool tail_doomed = false;   // the last admitted request will fail (its history is bad)
+    void* last_out = nullptr;   // output buffer of the last admitted request
   };
   struct Pending {
     uint64_t id, stream_id;
@@ -113,11 +132,15 @@ class Scheduler {
     int slot;
     std::vector<Item> items;
     std::vector<int64_t> t_submit, t_admit;
+    std::vector<char> doomed;   // item reads history that a failed request did not write
     int64_t t_start;
     int launch_rc;
+    double cost;
+    int64_t est_begin, est_end;  // expected device start and end
   };
 
   void loop();
+  bool start_now_locked(int64_t now);
   void admit_locked(std::vector<Item>& items, std::vector<int64_t>& ts, std::vector<int64_t>& ta);
   void finish_locked(Batch& b, int status);
   void free_stream_locked(uint64_t id);
@@ -134,6 +157,8 @@ class Scheduler {
   Stats st_{};
   uint64_t next_id_ = 1;
   bool running_ = true;
+  double ns_per_cost_ = 0.0;     // running average of device time per unit cost (0: none yet)
+  int64_t last_done_ = 0;        // when the last batch was seen finished
   std::thread thread_;
 };
 

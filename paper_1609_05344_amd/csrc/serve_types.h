@@ -27,7 +27,8 @@ struct ServeItem {
   int taa_tile_begin;           // first global resolve tile of this request
   int pad[3];
   void* cur;                    // [H][W] float4 scratch: this frame before resolve
-  void* hist;                   // [H][W] float4 history (stream state)
+  const void* hist_in;          // [H][W] float4 history read by the resolve
+  void* hist_out;               // [H][W] float4 history kept by the library (or null)
   void* out;                    // [H][W] float4 caller output
 };
 

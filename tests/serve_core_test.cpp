@@ -25,21 +25,30 @@ using namespace cloud::serve;
     }                                                                    \
   } while (0)
 
-// Batches finish after `delay_polls` queries. Records what it saw and checks
-// the scheduler's promises: a stream is never in two in-flight batches, and
-// memory is only handed out within the budget.
+// Batches finish after `delay_polls` queries, or, with batch_ns set, like an
+// in-order device: a batch runs from the later of its launch and the previous
+// batch's end for base_ns + batch_ns per request. Records what it saw and
+// checks the scheduler's promises: a stream is never twice in one batch nor
+// in more in-flight batches than the pipeline allows, its requests reach the
+// device in submission order, and memory is only handed out within the
+// budget.
 class FakeExecutor : public Executor {
  public:
   std::mutex mu;
   int delay_polls = 3;
+  int64_t base_ns = 0, batch_ns = 0;  // > 0: timed, in-order batches
+  int max_per_stream = 1;             // requests of a stream in flight
   int fail_launch_every = 0;          // every n-th launch fails (0: never)
   int fail_query_every = 0;           // every n-th batch reports a device error
   std::map<int, std::vector<Item>> slots;
   std::map<int, int> polls;
-  std::set<uint64_t> inflight_streams;
+  std::map<int, int64_t> ends;
+  std::map<uint64_t, int> inflight_streams;
+  std::map<uint64_t, uint64_t> last_request;
   std::vector<std::vector<Item>> history;
   size_t live_bytes = 0, peak_bytes = 0;
-  int launches = 0, queries_failed = 0;
+  int launches = 0, queries_failed = 0, peak_per_stream = 0;
+  int64_t device_end = 0;
   std::atomic<int> allocs{0}, releases{0};
 
   size_t stream_bytes(int w, int h) override { return (size_t)w * h * 32; }
@@ -63,27 +72,40 @@ class FakeExecutor : public Executor {
     std::lock_guard<std::mutex> lk(mu);
     launches++;
     CHECK(slots.find(slot) == slots.end());
+    std::set<uint64_t> in_batch;
     for (const Item& it : items) {
-      CHECK(inflight_streams.insert(it.stream_id).second);   // one per stream
+      CHECK(in_batch.insert(it.stream_id).second);               // one per stream and batch
+      CHECK(++inflight_streams[it.stream_id] <= max_per_stream);
+      peak_per_stream = std::max(peak_per_stream, inflight_streams[it.stream_id]);
+      CHECK(it.request_id > last_request[it.stream_id]);         // in submission order
+      last_request[it.stream_id] = it.request_id;
       CHECK(it.stream_mem != nullptr);
       // the output buffer and stream memory are touched like a device would
       static_cast<unsigned char*>(it.stream_mem)[0] = (unsigned char)it.frame;
     }
     history.push_back(items);
     if (fail_launch_every && launches % fail_launch_every == 0) {
-      for (const Item& it : items) inflight_streams.erase(it.stream_id);
+      for (const Item& it : items) inflight_streams[it.stream_id]--;
       return CLOUD_E_HIP;
     }
     slots[slot] = items;
     polls[slot] = 0;
+    if (batch_ns > 0) {
+      device_end = std::max(device_end, now_ns()) + base_ns + batch_ns * (int64_t)items.size();
+      ends[slot] = device_end;
+    }
     return 0;
   }
   int query(int slot) override {
     std::lock_guard<std::mutex> lk(mu);
     auto it = slots.find(slot);
     CHECK(it != slots.end());
-    if (++polls[slot] < delay_polls) return 0;
-    for (const Item& x : it->second) inflight_streams.erase(x.stream_id);
+    if (batch_ns > 0) {
+      if (now_ns() < ends[slot]) return 0;
+    } else if (++polls[slot] < delay_polls) {
+      return 0;
+    }
+    for (const Item& x : it->second) inflight_streams[x.stream_id]--;
     slots.erase(it);
     if (fail_query_every && ++queries_failed % fail_query_every == 0) return CLOUD_E_HIP;
     return 1;
@@ -113,6 +135,13 @@ static uint64_t submit(Scheduler& s, uint64_t sid, int w, int h, uint32_t frame,
   int r = s.submit(sid, w, h, frame, nullptr, std::vector<unsigned char>(8, 1), &id, &msg);
   if (rc) *rc = r;
   else CHECK(r == 0);
+  return id;
+}
+
+static uint64_t submit_out(Scheduler& s, uint64_t sid, int w, int h, uint32_t frame, void* out) {
+  uint64_t id = 0;
+  std::string msg;
+  CHECK(s.submit(sid, w, h, frame, out, std::vector<unsigned char>(8, 1), &id, &msg) == 0);
   return id;
 }
 
@@ -319,6 +348,137 @@ static void test_concurrent_clients() {
   printf("concurrent_clients ok\n");
 }
 
+// Pipelined streams on an in-order device: up to two requests of a stream in
+// flight, in consecutive batches, each resolving against the history of the
+// one before it (no reset after a stream's first request) and naming that
+// one's output buffer.
+static void test_pipeline() {
+  FakeExecutor ex;
+  ex.base_ns = 2000000;
+  ex.batch_ns = 200000;
+  ex.max_per_stream = 2;
+  Config cfg;
+  cfg.budget_bytes = 1 << 30;
+  cfg.pipeline = 2;
+  static char bufs[4][8];
+  {
+    Scheduler s(&ex, cfg);
+    std::map<uint64_t, std::vector<uint64_t>> ids;
+    for (uint32_t f = 0; f < 8; ++f)
+      for (uint64_t sid = 1; sid <= 4; ++sid)
+        ids[sid].push_back(submit_out(s, sid, 8, 8, f + 1, &bufs[sid - 1][f]));
+    auto got = drain(s, 32);
+    CHECK(got.size() == 32);
+    std::map<uint64_t, std::vector<uint64_t>> seen;
+    for (auto& c : got) {
+      CHECK(c.status == 0);
+      seen[c.stream_id].push_back(c.request_id);
+    }
+    CHECK(seen == ids);
+    std::map<uint64_t, void*> last_out;
+    for (auto& batch : ex.history)
+      for (auto& it : batch) {
+        const bool first = !last_out.count(it.stream_id);
+        CHECK(it.reset_history == first);
+        CHECK(it.prev_out == (first ? nullptr : last_out[it.stream_id]));
+        last_out[it.stream_id] = it.out;
+      }
+    CHECK(ex.peak_per_stream == 2);
+  }
+  CHECK(ex.live_bytes == 0 && ex.allocs == ex.releases);
+  printf("pipeline ok\n");
+}
+
+// A failed request fails the requests of its stream already in flight behind
+// it that resolve against its history; the stream's next admitted request
+// starts a fresh history.
+static void test_pipeline_failure() {
+  FakeExecutor ex;
+  ex.delay_polls = 2;
+  ex.max_per_stream = 2;
+  ex.fail_query_every = 3;
+  Config cfg;
+  cfg.budget_bytes = 1 << 30;
+  cfg.pipeline = 2;
+  Scheduler s(&ex, cfg);
+  for (uint32_t f = 1; f <= 12; ++f)
+    for (uint64_t sid = 1; sid <= 3; ++sid) submit(s, sid, 8, 8, f);
+  auto got = drain(s, 36);
+  CHECK(got.size() == 36);
+  std::map<uint64_t, int> status_by_id;
+  int failed = 0;
+  for (auto& c : got) {
+    status_by_id[c.request_id] = c.status;
+    if (c.status) failed++;
+  }
+  std::map<uint64_t, int> prev;   // status of the stream's previous request
+  int reset_after_failure = 0;
+  for (auto& batch : ex.history)
+    for (auto& it : batch) {
+      const int st = status_by_id[it.request_id];
+      if (prev.count(it.stream_id) && prev[it.stream_id] != 0) {
+        if (it.reset_history) reset_after_failure++;
+        else CHECK(st != 0);
+      }
+      prev[it.stream_id] = st;
+    }
+  CHECK(failed > 0 && failed < 36 && reset_after_failure > 0);
+  CHECK(s.stats().failed == (uint64_t)failed);
+  printf("pipeline_failure ok (%d failed)\n", failed);
+}
+
+// Closed-loop streams with `window` requests each in flight on a timed
+// in-order device; mean requests per batch after the first few batches.
+static double closed_loop_batch(int64_t lead_ns, int window) {
+  FakeExecutor ex;
+  ex.base_ns = 3000000;
+  ex.batch_ns = 400000;
+  ex.max_per_stream = window;
+  Config cfg;
+  cfg.budget_bytes = 1 << 30;
+  cfg.pipeline = window;
+  cfg.lead_ns = lead_ns;
+  const int n = 8, frames = 14;
+  std::vector<Completion> got;
+  {
+    Scheduler s(&ex, cfg);
+    std::map<uint64_t, uint32_t> sent;
+    for (uint64_t sid = 0; sid < (uint64_t)n; ++sid)
+      for (int w = 0; w < window; ++w) submit(s, sid, 8, 8, ++sent[sid]);
+    auto t0 = std::chrono::steady_clock::now();
+    while ((int)got.size() < n * frames) {
+      Completion c[64];
+      int k = 0;
+      s.poll(c, 64, &k);
+      for (int i = 0; i < k; ++i) {
+        CHECK(c[i].status == 0);
+        got.push_back(c[i]);
+        if (sent[c[i].stream_id] < (uint32_t)frames) submit(s, c[i].stream_id, 8, 8, ++sent[c[i].stream_id]);
+      }
+      if (!k) s.wait(2000000);
+      CHECK(std::chrono::steady_clock::now() - t0 < std::chrono::seconds(20));
+    }
+  }
+  std::lock_guard<std::mutex> lk(ex.mu);
+  size_t items = 0, batches = 0;
+  for (size_t b = 4; b + 1 < ex.history.size(); ++b, ++batches) items += ex.history[b].size();
+  CHECK(batches > 0);
+  return (double)items / batches;
+}
+
+static void test_start_lead() {
+  // one request a stream in flight: the streams split into two groups that
+  // take turns, and with the lead each batch holds a whole group
+  const double eager1 = closed_loop_batch(-1, 1), lead1 = closed_loop_batch(500000, 1);
+  // two in flight: with the lead every batch holds every stream
+  const double eager2 = closed_loop_batch(-1, 2), lead2 = closed_loop_batch(500000, 2);
+  printf("start_lead: requests a batch, at once / with the lead: window 1 %.2f / %.2f, "
+         "window 2 %.2f / %.2f\n", eager1, lead1, eager2, lead2);
+  CHECK(lead1 >= 3.5);
+  CHECK(lead2 >= 7.0);
+  printf("start_lead ok\n");
+}
+
 int main() {
   test_order_and_reset();
   test_budget_admission();
@@ -326,6 +486,9 @@ int main() {
   test_close_and_destroy_cancel();
   test_failures();
   test_concurrent_clients();
+  test_pipeline();
+  test_pipeline_failure();
+  test_start_lead();
   printf("ALL OK\n");
   return 0;
 }

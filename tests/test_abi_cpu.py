@@ -37,17 +37,18 @@ def test_exports_every_declared_function(lib):
     assert len(names) >= 6
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.cloud_abi_version() == _lib.ABI_VERSION == 3
+    assert lib.cloud_abi_version() == _lib.ABI_VERSION == 4
 
 
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "cloud.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cloud_volume),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cloud_volume),"
         " sizeof(cloud_camera), sizeof(cloud_params), offsetof(cloud_volume, layout),"
         " offsetof(cloud_params, t_eps), offsetof(cloud_volume, detail),"
-        " sizeof(cloud_serve_config), offsetof(cloud_serve_config, queues));return 0;}\n")
+        " sizeof(cloud_serve_config), offsetof(cloud_serve_config, queues),"
+        " offsetof(cloud_serve_config, start_lead_us));return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True)
@@ -56,7 +57,8 @@ def test_struct_layout_matches_header(tmp_path):
     assert got == [ctypes.sizeof(_lib.cloud_volume), ctypes.sizeof(_lib.cloud_camera),
                    ctypes.sizeof(_lib.cloud_params), _lib.cloud_volume.layout.offset,
                    _lib.cloud_params.t_eps.offset, _lib.cloud_volume.detail.offset,
-                   ctypes.sizeof(_lib.cloud_serve_config), _lib.cloud_serve_config.queues.offset]
+                   ctypes.sizeof(_lib.cloud_serve_config), _lib.cloud_serve_config.queues.offset,
+                   _lib.cloud_serve_config.start_lead_us.offset]
 
 
 def test_argument_errors_before_any_launch(lib):
@@ -122,7 +124,8 @@ def test_tune_keys_checked(lib):
     try:
         for key, good, bad in (("supertile", (-1, 0, 4, 64), (-2, 65)),
                                ("xcd_run", (-1, 0, 16, 65536), (-2, 65537)),
-                               ("taa_tile", (16, 32, 64), (0, 8, 128))):
+                               ("taa_tile", (16, 32, 64), (0, 8, 128)),
+                               ("serve_blocks_per_cu", (0, 1, 4, 64), (-1, 65))):
             for v in good:
                 assert ok(key.encode(), v) == _lib.CLOUD_OK, (key, v)
             for v in bad:
@@ -134,6 +137,7 @@ def test_tune_keys_checked(lib):
         ok(b"supertile", -1)
         ok(b"xcd_run", -1)
         ok(b"taa_tile", 32)
+        ok(b"serve_blocks_per_cu", 0)
 
 
 def test_binding_checks_tensor_layout():

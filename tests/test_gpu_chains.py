@@ -112,19 +112,23 @@ def finish(srv, ids, timeout=120.0):
     return got
 
 
-@pytest.mark.parametrize("queues,graphs", [(1, True), (2, True), (1, False), (2, False)])
-def test_served_fp16_quad_1080p_chains(cf, queues, graphs):
+@pytest.mark.parametrize("queues,graphs,hio", [
+    (1, True, False), (2, True, False), (1, False, False), (2, False, False),
+    (1, True, True), (2, False, True)])
+def test_served_fp16_quad_1080p_chains(cf, queues, graphs, hio):
     """The served benchmark's configuration: FP16 quad + occupancy volume, 8
     camera streams at 1920x1080, 4 chained frames each, submitted together
-    so that the batches mix streams. Every served frame is bitwise the plain
-    chain's (cloud_render + cloud_taa_resolve on the same volume), and the
-    last frames of two streams match the oracle at sampled pixels."""
+    so that the batches mix streams (with one queue, two frames of a stream
+    in flight), the history kept by the library or read from the previous
+    output (hio). Every served frame is bitwise the plain chain's
+    (cloud_render + cloud_taa_resolve on the same volume), and the last
+    frames of two streams match the oracle at sampled pixels."""
     import torch
     w = scenes.workload("H")
     W, H = w.width, w.height
     n_streams, frames = 8, [400, 401, 402, 403]
     say(f"serve: {n_streams} streams x {len(frames)} frames at 1080p, FP16 quad + occupancy, "
-        f"queues={queues} graphs={graphs}")
+        f"queues={queues} graphs={graphs} history_in_output={hio}")
     sc = scenes.make_scene(w, dtype="f16")
     vol = cf.device_volume(sc, layout="quad", occupancy=True)
 
@@ -133,7 +137,7 @@ def test_served_fp16_quad_1080p_chains(cf, queues, graphs):
 
     outs = [[torch.zeros((H, W, 4), device="cuda") for _ in frames] for _ in range(n_streams)]
     with cf.Server(vol, budget_bytes=4 << 30, max_batch=64, queues=queues,
-                   use_graphs=graphs) as srv:
+                   use_graphs=graphs, history_in_output=hio) as srv:
         ids = []
         for k, f in enumerate(frames):
             for s in range(n_streams):

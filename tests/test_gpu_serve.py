@@ -136,6 +136,76 @@ def test_alone_equals_mixed(cf, vol, use_graphs):
             assert np.array_equal(to_np(x[6]), ref[k]), (s, k)
 
 
+@pytest.mark.parametrize("same_buffer,queues", [(False, 1), (True, 1), (False, 2)])
+def test_history_in_output(cf, vol, same_buffer, queues):
+    """history_in_output: each stream resolves against its previous frame's
+    output buffer instead of a library copy. Frames are bitwise the plain
+    chain's, with one buffer per frame or one buffer reused for every frame
+    (resolved in place), with the resolve on the render's queue or on its
+    own; the stream state holds no history."""
+    import torch
+    say(f"serve: history in the outputs (same_buffer={same_buffer}, queues={queues})")
+    w = scenes.workload("C2")
+    W, H = 128, 72
+    frames = [0, 1, 2, 3, 4, 5]
+    n = 6
+    cams = {s: [scenes.orbit_camera(1.0, 40.0 * s + f, 8.0) for f in frames] for s in range(n)}
+    refs = {s: plain_chain(cf, vol, cams[s], w.params, W, H, frames) for s in range(n)}
+    if same_buffer:
+        bufs = {s: [torch.zeros((H, W, 4), device="cuda")] * len(frames) for s in range(n)}
+    else:
+        bufs = {s: [torch.zeros((H, W, 4), device="cuda") for _ in frames] for s in range(n)}
+    with cf.Server(vol, budget_bytes=1 << 30, max_batch=8, queues=queues,
+                   history_in_output=True) as srv:
+        ids = [srv.submit(s, cams[s][k], w.params, W, H, f, bufs[s][k])
+               for k, f in enumerate(frames) for s in range(n)]
+        got = finish(srv, ids)
+        assert all(c["status"] == 0 for c in got.values())
+        st = srv.stats()
+        # one scratch frame a stream (two with the resolve queue), no history
+        assert st["bytes_in_use"] == n * queues * (((W * H * 16 + 255) // 256) * 256)
+    torch.cuda.synchronize()
+    for s in range(n):
+        if same_buffer:
+            assert np.array_equal(to_np(bufs[s][0]), refs[s][-1]), s
+        else:
+            for k in range(len(frames)):
+                assert np.array_equal(to_np(bufs[s][k]), refs[s][k]), (s, k)
+
+
+@pytest.mark.parametrize("lead_us", [-1, 0, 5000])
+def test_start_lead_keeps_results(cf, vol, lead_us):
+    """The batch start policy changes only when batches start: a mix of
+    streams submitted as they complete gives the plain chain's frames."""
+    import torch
+    say(f"serve: start lead {lead_us} us, closed loop of 10 streams")
+    w = scenes.workload("C2")
+    W, H, n, nf = 96, 64, 10, 5
+    cams = {s: [scenes.orbit_camera(1.0, 30.0 * s + f, 6.0) for f in range(nf)] for s in range(n)}
+    outs = {s: [torch.zeros((H, W, 4), device="cuda") for _ in range(nf)] for s in range(n)}
+    with cf.Server(vol, budget_bytes=1 << 30, start_lead_us=lead_us) as srv:
+        sent = {s: 0 for s in range(n)}
+        for s in range(n):
+            srv.submit(s, cams[s][0], w.params, W, H, 0, outs[s][0])
+        done, t0 = 0, time.time()
+        while done < n * nf:
+            for c in srv.poll(256):
+                assert c["status"] == 0
+                done += 1
+                s = c["stream_id"]
+                sent[s] += 1
+                if sent[s] < nf:
+                    k = sent[s]
+                    srv.submit(s, cams[s][k], w.params, W, H, k, outs[s][k])
+            srv.wait(0.01)
+            assert time.time() - t0 < 60.0, "serving timed out"
+    torch.cuda.synchronize()
+    for s in (0, 4, 9):
+        ref = plain_chain(cf, vol, cams[s], w.params, W, H, list(range(nf)))
+        for k in range(nf):
+            assert np.array_equal(to_np(outs[s][k]), ref[k]), (s, k)
+
+
 def test_budget_admission_and_close(cf, vol):
     import torch
     say("serve: admission under a small budget, close_stream frees room")

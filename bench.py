@@ -40,6 +40,10 @@ TIMED_FIRST = 400
 TIMED_PERIOD = 20
 # untimed frames before the timed ones, at least (warm-up plus settling)
 SETTLE_FRAMES = 200
+# timed steps that carry timing events (every EVENT_EVERY-th, from the first):
+# an event is a packet between kernels that costs 1-2 us, so the others go
+# without
+EVENT_EVERY = 4
 # Arithmetic type of the path for each storage type: every optical depth,
 # transmittance, exponential and colour is float32; 16-bit storage adds
 # 16-bit texels (and, for FP16, 16-bit x-lerp weights in dot products).
@@ -121,6 +125,16 @@ class TimingEvent:
 def timed_frames(steps: int) -> list:
     """Orbit frames of the timed steps: the fixed window, cycled."""
     return [TIMED_FIRST + k % TIMED_PERIOD for k in range(steps)]
+
+
+def event_steps(steps: int) -> list:
+    """Timed steps that carry timing events: every EVENT_EVERY-th from step
+    0, the sample shifted by one window position each pass through the
+    window, so that a long run times the render on every frame of it."""
+    sampled = list(range(0, steps, EVENT_EVERY))
+    if TIMED_PERIOD % EVENT_EVERY == 0:
+        sampled = [k + (k // TIMED_PERIOD) % EVENT_EVERY for k in sampled]
+    return [k for k in sampled if k < steps]
 
 
 def warm_frames(warmup: int) -> list:
@@ -256,21 +270,25 @@ OPS_PER_HIT = 15
 
 
 def algorithmic_ops(cf, torch, np, w, vol, p, frames) -> dict:
-    """Units of work per frame (mean over the frames): executed lookups,
-    primary samples, lit samples, pixels and hit pixels, from the library's
-    lookup trace (outside the timed launches), and the lane operations they
-    need."""
+    """Units of work per frame (mean over the frames, which may repeat):
+    executed lookups, primary samples, lit samples, pixels and hit pixels,
+    from the library's lookup trace (outside the timed launches), and the
+    lane operations they need."""
     if p.steps > 32 or w.detail_n:
         return None
     V, W, H = w.views, w.width, w.height
-    prim = lit = hit = 0
-    for f in frames:
+    per_frame = {}
+    for f in sorted(set(frames)):
         tr = cf.cloud_lookup_trace(vol, [w.camera(f, view=v) for v in range(V)], p, f, W, H)
         t = tr.cpu().numpy().view(np.uint32).reshape(-1, 2)
-        prim += int(t[:, 0].astype(np.int64).sum())
         m = t[:, 1].astype(np.uint64)
-        lit += int(sum(((m >> np.uint64(k)) & np.uint64(1)).sum() for k in range(32)))
-        hit += int((t[:, 0] > 0).sum())
+        per_frame[f] = (int(t[:, 0].astype(np.int64).sum()),
+                        int(sum(((m >> np.uint64(k)) & np.uint64(1)).sum() for k in range(32))),
+                        int((t[:, 0] > 0).sum()))
+    frames = list(frames)
+    prim = sum(per_frame[f][0] for f in frames)
+    lit = sum(per_frame[f][1] for f in frames)
+    hit = sum(per_frame[f][2] for f in frames)
     n = len(frames)
     units = {"lookups": (prim + p.light_steps * lit) / n, "primary_samples": prim / n,
              "lit_samples": lit / n, "pixels": V * W * H, "hit_pixels": hit / n}
@@ -896,9 +914,10 @@ def main():
         DW, DH = w.display
         sky = torch.tensor(scenes.sky_background(DW, DH), device=dev)
         frame_out = torch.empty((DH, DW, 4), device=dev)
-    # per timed frame: before and after the render (the next frame's first
-    # event, or `end`, closes the frame)
-    ev = [(TimingEvent(), TimingEvent()) for _ in range(args.steps)]
+    # per sampled timed frame (every EVENT_EVERY-th): before and after the
+    # render; the next sampled frame's first event, or `end`, closes its group
+    sampled = event_steps(args.steps)
+    ev = {k: (TimingEvent(), TimingEvent()) for k in sampled}
     end = TimingEvent()
 
     def frame(f, events=None):
@@ -936,14 +955,17 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k, f in enumerate(timed):
-        frame(f, ev[k])
+        frame(f, ev.get(k))
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    render_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    starts = [a for a, _ in ev] + [end]
-    frame_ms = np.array([starts[k].elapsed_time(starts[k + 1]) for k in range(args.steps)])
+    render_ms = float(np.mean([a.elapsed_time(b) for a, b in ev.values()]))
+    # mean frame time of each group of EVENT_EVERY frames (the last may be shorter)
+    starts = [ev[k][0] for k in sampled] + [end]
+    bounds = sampled + [args.steps]
+    frame_ms = np.array([starts[i].elapsed_time(starts[i + 1]) / (bounds[i + 1] - bounds[i])
+                         for i in range(len(sampled))])
     lk_timed = int(sum(counts[k % TIMED_PERIOD] for k in range(args.steps)))
     lk_frame = lk_timed / args.steps
     ms_per_step = wall * 1e3 / args.steps
@@ -951,7 +973,9 @@ def main():
 
     elem = 4 if args.dtype == "f32" else 2
     bytes_per_lookup = 8 * elem * (2 if w.detail_n else 1)   # base (+ detail) footprint
-    alg = algorithmic_ops(cf, torch, np, w, vol, p, range(TIMED_FIRST, TIMED_FIRST + TIMED_PERIOD))
+    # the roofline's work figures are for the frames whose render was timed
+    alg = algorithmic_ops(cf, torch, np, w, vol, p, [timed[k] for k in sampled])
+    lk_sampled = float(np.mean([counts[k % TIMED_PERIOD] for k in sampled]))
     traffic_key = counter_config(w.name, args.dtype, args.layout, not args.no_occupancy)
     line = {
         "metric": "Gsamples/s @1080p 8-step+TAA (executed trilinear density lookups per second; "
@@ -976,12 +1000,16 @@ def main():
                    "occupancy_skip": not args.no_occupancy,
                    "lookups_per_frame": round(lk_frame),
                    "nominal_lookups_per_frame": V * W * H * p.steps * (1 + p.light_steps)},
-        "roofline": roofline(recorded_counters(traffic_key), alg, render_ms, lk_frame,
+        "roofline": roofline(recorded_counters(traffic_key), alg, render_ms, lk_sampled,
                              bytes_per_lookup),
         "cpu_baseline": cpu,
-        # HIP-event time from each timed frame's start to the next one's
+        # HIP-event time per frame over each group of EVENT_EVERY timed
+        # frames; the render kernel's time (roofline) is timed on the first
+        # frame of each group
         "frame_ms": {"median": round(float(np.median(frame_ms)), 4),
-                     "p90": round(float(np.percentile(frame_ms, 90)), 4)},
+                     "p90": round(float(np.percentile(frame_ms, 90)), 4),
+                     "frames_per_group": EVENT_EVERY},
+        "render_kernel_timed_frames": len(sampled),
     }
     if not args.no_replay:
         line["offset_replay"] = offset_replay(cf, torch, np, w, vol, p,

@@ -72,3 +72,15 @@ def test_oracle_subset_counts_the_subset_lookups():
     _, lk = O.render(vol, w.camera(0), w.params, w.width, w.height, frame=0, pixels=pix,
                      return_lookups=True)
     assert r["pixels"] == 64 and r["lookups"] == lk and r["steps"] == 128
+
+
+def test_event_sample_covers_the_window():
+    """Timing events go on a sample of the timed steps: distinct, in order,
+    starting at the first step, about one in EVENT_EVERY, and over a long run
+    every frame of the timed window is among them."""
+    for steps in (1, 5, 20, 21, 300, 1000):
+        s = bench.event_steps(steps)
+        assert s[0] == 0 and s == sorted(set(s)) and s[-1] < steps
+        assert abs(len(s) - len(range(0, steps, bench.EVENT_EVERY))) <= 1
+    frames = [bench.timed_frames(300)[k] for k in bench.event_steps(300)]
+    assert set(frames) == set(bench.timed_frames(bench.TIMED_PERIOD))

@@ -10,7 +10,11 @@ alpha >= 0.01. One reprojected resolve is held to the float32 gate (1e-4): the
 projected coordinate carries about 1e-4 pixels of float32 error at these
 widths, times a history gradient below 0.5 per pixel. A chain of resolves
 feeds that error back through the history with weight 1 - blend per frame, so
-a chain is held to 1e-4 / blend = 1e-3 max-abs and 2e-5 mean-abs.
+the analysis bounds a chain by 1e-4 / blend = 1e-3 where such an error meets
+a sharp history edge every frame. On these seeded orbits the chain stays at
+the single frame's render error (max-abs 3.6e-5 on the first frame, falling
+to about 3e-6 as the history settles), so chains are held to the float32
+gate itself, 1e-4 max-abs, and 2e-6 mean-abs.
 """
 
 import sys
@@ -100,10 +104,10 @@ def test_reproject_one_step_full_frame(cf):
     assert np.max(np.abs(want - plain)) > 1e-2
 
 
-def test_reproject_chain_orbit(cf):
+@pytest.mark.parametrize("W,H,F", [(320, 180, 16), (640, 360, 8)])
+def test_reproject_chain_orbit(cf, W, H, F):
     import torch
     w = scenes.workload("C2")
-    W, H, F = 320, 180, 8
     say(f"C2 {W}x{H}: {F}-frame orbit, render_depth + reprojected resolve chain vs oracle")
     sc = scenes.make_scene(w)
     ov = oracle_volume(sc)
@@ -119,7 +123,8 @@ def test_reproject_chain_orbit(cf):
         want_hist = O.taa_resolve_reproject(o, want_hist, od, cam, prev, w.taa_blend, f)
         got = to_np(bufs[f % 2])
         err = np.abs(got.astype(np.float64) - want_hist)
-        assert err.max() < 1e-3 and err.mean() < 2e-5, (f, err.max(), err.mean())
+        say(f"  frame {f}: max-abs {err.max():.3g}, mean-abs {err.mean():.3g}")
+        assert err.max() < FP32_TOL and err.mean() < 2e-6, (f, err.max(), err.mean())
 
 
 def test_reproject_still_camera_matches_plain_resolve(cf):

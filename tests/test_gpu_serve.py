@@ -206,6 +206,32 @@ def test_start_lead_keeps_results(cf, vol, lead_us):
             assert np.array_equal(to_np(outs[s][k]), ref[k]), (s, k)
 
 
+@pytest.mark.parametrize("cap", [1, 4])
+def test_render_workgroup_cap_keeps_results(cf, vol, cap):
+    """serve_blocks_per_cu changes only how many persistent render workgroups
+    a CU holds: the served frames stay the plain chain's."""
+    import torch
+    say(f"serve: {cap} render workgroups per CU, 6 streams x 3 frames")
+    w = scenes.workload("C2")
+    W, H, n, frames = 200, 120, 6, [0, 1, 2]
+    cams = {s: [scenes.orbit_camera(1.0, 50.0 * s + f, 7.0) for f in frames] for s in range(n)}
+    outs = {s: [torch.zeros((H, W, 4), device="cuda") for _ in frames] for s in range(n)}
+    cf.cloud_tune("serve_blocks_per_cu", cap)
+    try:
+        with cf.Server(vol, budget_bytes=1 << 30) as srv:
+            ids = [srv.submit(s, cams[s][k], w.params, W, H, f, outs[s][k])
+                   for k, f in enumerate(frames) for s in range(n)]
+            got = finish(srv, ids)
+            assert all(c["status"] == 0 for c in got.values())
+    finally:
+        cf.cloud_tune("serve_blocks_per_cu", 0)
+    torch.cuda.synchronize()
+    for s in (0, 5):
+        ref = plain_chain(cf, vol, cams[s], w.params, W, H, frames)
+        for k in range(len(frames)):
+            assert np.array_equal(to_np(outs[s][k]), ref[k]), (s, k)
+
+
 def test_budget_admission_and_close(cf, vol):
     import torch
     say("serve: admission under a small budget, close_stream frees room")

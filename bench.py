@@ -788,8 +788,8 @@ def main():
                          "a library copy of the history")
     ap.add_argument("--serve-blocks-per-cu", type=int, default=0,
                     help="cap on the persistent serving render's workgroups per CU in the "
-                         "closed-loop served leg (0: as many as fit; the open-loop mix always "
-                         "runs uncapped)")
+                         "closed-loop served leg (0: the server's automatic choice; the "
+                         "open-loop mix always runs with it)")
     ap.add_argument("--serve-lead-us", type=int, default=0,
                     help="batch start lead of the server (0: its default; -1: start each "
                          "batch as soon as a slot is free)")
@@ -1034,7 +1034,7 @@ def main():
                                 f"{n_streams} stream cameras" if plain_views else
                                 "the timed plain step")
         served["speedup_vs_plain"] = round(served["frames_per_s"] / served["plain_frames_per_s"], 3)
-        served["serve_blocks_per_cu"] = args.serve_blocks_per_cu
+        served["serve_blocks_per_cu"] = args.serve_blocks_per_cu or "auto"
         line["served"] = served
     if not args.no_served and not args.no_c4:
         # the serving form's latency metric: 64 streams of mixed resolutions and

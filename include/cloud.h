@@ -372,9 +372,9 @@ int cloud_volume_occupancy(const cloud_volume* dense, uint32_t* dst, uint64_t ds
  *  "render_blocks_per_cu" (0..64, default 0 = no cap) -- at most this many
  *      render workgroups resident per CU, enforced by reserving LDS at
  *      launch (CLOUD_E_INVALID when the device's LDS cannot express it).
- *  "serve_blocks_per_cu" (0..64, default 0 = as many as fit) -- the
- *      persistent serving render's workgroups per CU, read by
- *      cloud_serve_create. */
+ *  "serve_blocks_per_cu" (0..64, default 0 = automatic: 4 for a stored
+ *      volume above 512 MiB, else as many as fit) -- the persistent serving
+ *      render's workgroups per CU, read by cloud_serve_create. */
 int cloud_tune(const char* key, int32_t value);
 
 /* Checks that [ptr, ptr + bytes) lies inside one HIP device allocation: the

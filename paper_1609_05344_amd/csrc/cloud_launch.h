@@ -19,7 +19,7 @@ struct Tuning {
   // bricked packed layouts every measured cap was slower)
   int render_blocks_per_cu = 0;
   // cap on the persistent serving render's workgroups per CU, read when a
-  // server is created (0: as many as fit)
+  // server is created (0: automatic, by the stored volume's size)
   int serve_blocks_per_cu = 0;
 };
 Tuning& tuning();

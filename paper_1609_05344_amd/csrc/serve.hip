@@ -15,6 +15,7 @@
 #include "cloud_prepare.h"
 #include "serve_core.h"
 #include "serve_types.h"
+#include "stream_io.h"
 
 namespace cloud {
 
@@ -133,8 +134,8 @@ __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* __rest
     if (it.reset) {
       if (inside) {
         const float4 v = cur[p];
-        if (hist_out) hist_out[p] = v;
-        out[p] = v;
+        if (hist_out) store_stream(hist_out + p, v);
+        store_stream(out + p, v);
       }
       continue;
     }
@@ -157,15 +158,15 @@ __global__ __launch_bounds__(256) void serve_taa_kernel(const ServeTable* __rest
           hi.x = fmaxf(hi.x, v.x); hi.y = fmaxf(hi.y, v.y); hi.z = fmaxf(hi.z, v.z); hi.w = fmaxf(hi.w, v.w);
         }
       }
-      float4 h = hist_in[p];
+      float4 h = load_stream(hist_in + p);
       h.x = fminf(fmaxf(h.x, lo.x), hi.x);
       h.y = fminf(fmaxf(h.y, lo.y), hi.y);
       h.z = fminf(fmaxf(h.z, lo.z), hi.z);
       h.w = fminf(fmaxf(h.w, lo.w), hi.w);
       const float4 r = make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
                                    fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w));
-      if (hist_out) hist_out[p] = r;
-      out[p] = r;
+      if (hist_out) store_stream(hist_out + p, r);
+      store_stream(out + p, r);
     }
     __syncthreads();
   }

@@ -3,6 +3,7 @@
 
 #include "cloud_device.h"
 #include "cloud_launch.h"
+#include "stream_io.h"
 
 namespace cloud {
 
@@ -51,13 +52,13 @@ __global__ __launch_bounds__(256) void taa_kernel(const float4* __restrict__ cur
     }
   }
   const size_t p = (size_t)py * W + px;
-  float4 h = hist[p];
+  float4 h = load_stream(hist + p);
   h.x = fminf(fmaxf(h.x, lo.x), hi.x);
   h.y = fminf(fmaxf(h.y, lo.y), hi.y);
   h.z = fminf(fmaxf(h.z, lo.z), hi.z);
   h.w = fminf(fmaxf(h.w, lo.w), hi.w);
-  out[p] = make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
-                       fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w));
+  store_stream(out + p, make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
+                                    fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w)));
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
@@ -146,8 +147,8 @@ __global__ __launch_bounds__(256) void taa_reproject_kernel(const float4* __rest
   h.y = fminf(fmaxf(h.y, lo.y), hi.y);
   h.z = fminf(fmaxf(h.z, lo.z), hi.z);
   h.w = fminf(fmaxf(h.w, lo.w), hi.w);
-  out[p] = make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
-                       fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w));
+  store_stream(out + p, make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
+                                    fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w)));
 }
 
 // Contiguous XCD runs pay while the resolve's frames (current, history and

@@ -98,7 +98,10 @@ __global__ __launch_bounds__(256) void serve_render_kernel(DevVolume vol,
       const RayResult r = march<DT, LAYOUT, DETAIL, false>(vol, it.prm, it.cam.pos[0],
                                                            it.cam.pos[1], it.cam.pos[2], dx, dy,
                                                            dz, j);
-      as_global(it.cur)[(size_t)py * it.width + px] = make_float4(r.r, r.g, r.b, r.a);
+      // streamed: the batch's frames are resolved only after all of them
+      // are rendered, from memory, so caching them would only evict volume
+      store_stream(as_global(it.cur) + (size_t)py * it.width + px,
+                   make_float4(r.r, r.g, r.b, r.a));
     }
   }
 }

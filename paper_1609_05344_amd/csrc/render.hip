@@ -48,7 +48,11 @@ __global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams pr
                                                      float* __restrict__ depth) {
   constexpr bool COUNT = MODE == kCount;
   const int tiles_per_view = tiles_x * tiles_y;
-  const int tile = xcd_walk(blockIdx.x, gridDim.x, L);
+  // Odd frames walk the tiles mirrored (every XCD's runs stay compact), so a
+  // frame starts where the one before it ended, on the volume lines the
+  // last-level cache still holds.
+  int tile = xcd_walk(blockIdx.x, gridDim.x, L);
+  if (frame & 1u) tile = (int)gridDim.x - 1 - tile;
   const int view = tile / tiles_per_view;
   int tx, ty;
   supertile(tile - view * tiles_per_view, tiles_x, tiles_y, S, tx, ty);

@@ -283,22 +283,25 @@ def test_views_match_single_renders(cf, torch):
         assert np.array_equal(multi[v], single)
 
 
+@pytest.mark.parametrize("frame", [3, 4])
 @pytest.mark.parametrize("shape", [(1920, 1080, 1), (333, 77, 1), (200, 120, 5)])
-def test_tile_walks_render_identically(cf, torch, shape):
-    # the block -> tile walk (super-tile size, XCD interleave) only reorders
-    # work: every walk must write every pixel once, with the same values
+def test_tile_walks_render_identically(cf, torch, shape, frame):
+    # the block -> tile walk (super-tile size, XCD interleave, and its mirror
+    # on odd frames) only reorders work: every walk must write every pixel
+    # once, with the same values
     W, H, views = shape
-    say(f"tile walks: {views} x {W}x{H}, every setting bitwise equal to row-major")
+    say(f"tile walks: {views} x {W}x{H}, frame {frame}, every setting bitwise equal to row-major")
     w = scenes.workload("H")
     vol = cf.device_volume(scenes.make_scene(w, dtype="f16"), layout="oct", occupancy=True)
-    cams = [w.camera(3 + v) for v in range(views)]
+    cams = [w.camera(frame + v) for v in range(views)]
     results = {}
     try:
         for S, inter in ((0, 0), (-1, -1), (0, 16), (3, 7), (4, 16), (8, 64), (8, 0), (5, 1), (64, 4096)):
             cf.cloud_tune("supertile", S)
             cf.cloud_tune("xcd_run", inter)
             out = torch.full((views, H, W, 4), float("nan"), device="cuda")
-            results[(S, inter)] = to_np(cf.cloud_render_views(vol, cams, w.params, 3, W, H, out=out))
+            results[(S, inter)] = to_np(cf.cloud_render_views(vol, cams, w.params, frame, W, H,
+                                                              out=out))
     finally:
         cf.cloud_tune("supertile", -1)
         cf.cloud_tune("xcd_run", -1)

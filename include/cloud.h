@@ -414,10 +414,9 @@ int cloud_jitter_offsets(const uint32_t* pixel_xy, int64_t n, uint32_t frame_ind
  *
  * Stream state is library-owned: a scratch frame (two with queues = 2),
  * plus, unless history_in_output is set, the history (width x height x 16
- * bytes each, each rounded up to 256 bytes). It
- * is allocated when the stream's first request is admitted, counted against
- * hbm_budget_bytes, and freed by cloud_serve_close_stream or
- * cloud_serve_destroy. A stream's resolution is fixed by its first request.
+ * bytes each, rounded up to 256 bytes). It is allocated when the stream's
+ * first request is admitted, counted against hbm_budget_bytes, and freed by
+ * cloud_serve_close_stream or cloud_serve_destroy. A stream's resolution is fixed by its first request.
  * frame_index 0 (or a stream without valid history) copies the rendered frame
  * instead of resolving it.
  *
@@ -475,9 +474,10 @@ int cloud_serve_create(const cloud_volume* shared, const cloud_serve_config* cfg
 
 /* Queues one frame of stream stream_id. out_rgba: device [height][width][4]
  * float32, caller-owned, 16-byte aligned, not touched by the caller until
- * the request completes (with history_in_output, until the stream's next
- * request completes; it may be read). Returns CLOUD_E_BUSY when the queue is full (retry
- * later), CLOUD_E_NOMEM when this stream's state can never fit the budget,
+ * the request completes (with history_in_output: not written by the caller
+ * until the stream's next request completes; it may be read once this one
+ * has). Returns CLOUD_E_BUSY when the queue is full (retry later),
+ * CLOUD_E_NOMEM when this stream's state can never fit the budget,
  * CLOUD_E_INVALID for bad arguments or a resolution that differs from the
  * stream's first request. Camera and params are copied. */
 int cloud_serve_submit(cloud_server* server, uint64_t stream_id,
@@ -499,7 +499,7 @@ int cloud_serve_wait(cloud_server* server, int64_t timeout_ns);
 int cloud_serve_stats(cloud_server* server, cloud_serve_stats_t* out);
 
 /* Cancels the stream's queued requests (they complete as CLOUD_E_CANCELLED)
- * and frees its state once its in-flight request, if any, has finished.
+ * and frees its state once its in-flight requests, if any, have finished.
  * CLOUD_E_NOTFOUND for an unknown stream. */
 int cloud_serve_close_stream(cloud_server* server, uint64_t stream_id);
 

@@ -218,8 +218,8 @@ struct ReplayFetch<DT, LAYOUT_OCT | kLayoutTab> : ReplayOct<DT, true> {};
 constexpr int kReplayBatch = 8;   // slots whose fetches are in flight together
 
 // Replays the recorded slots of every wavefront on the render's launch shape
-// and tile walk (in the order of even frames; the render mirrors it on odd
-// ones), kReplayBatch slots at a time: their codes, then all their
+// and tile walk (in the order of even frames; on odd ones the render takes
+// each XCD's blocks in reverse), kReplayBatch slots at a time: their codes, then all their
 // fetches, then the folds. RANDOM: the same slots and lanes, each at a
 // uniformly random corner of the whole volume (no occupancy skip). Corners
 // are clamped into the volume and slot counts to max_slots, whatever the

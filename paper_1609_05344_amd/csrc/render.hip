@@ -48,11 +48,16 @@ __global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams pr
                                                      float* __restrict__ depth) {
   constexpr bool COUNT = MODE == kCount;
   const int tiles_per_view = tiles_x * tiles_y;
-  // Odd frames walk the tiles mirrored (every XCD's runs stay compact), so a
-  // frame starts where the one before it ended, on the volume lines the
-  // last-level cache still holds.
-  int tile = xcd_walk(blockIdx.x, gridDim.x, L);
-  if (frame & 1u) tile = (int)gridDim.x - 1 - tile;
+  // On odd frames each XCD takes its blocks in reverse order (blocks x,
+  // x + 8, ... are XCD x's), so a frame starts on the tiles each XCD ended
+  // the one before with, whose volume lines its L2 and the last-level cache
+  // still hold.
+  int b = blockIdx.x;
+  if (frame & 1u) {
+    const int x = b & 7, k = b >> 3, nx = ((int)gridDim.x - x + 7) >> 3;
+    b = 8 * (nx - 1 - k) + x;
+  }
+  const int tile = xcd_walk(b, gridDim.x, L);
   const int view = tile / tiles_per_view;
   int tx, ty;
   supertile(tile - view * tiles_per_view, tiles_x, tiles_y, S, tx, ty);

@@ -576,7 +576,8 @@ def served_closed_loop(cf, scenes, torch, w, dtype: str, layout: str, n_streams:
 
 def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: float = 1.0,
                    n_streams: int = 64, seed: int = 5344, ring: int = 4,
-                   budget_bytes: int = 64 << 30, queues: int = 1) -> dict:
+                   budget_bytes: int = 64 << 30, queues: int = 1,
+                   start_lead_us: int = 0) -> dict:
     """Open-loop serving load: n_streams camera streams, each with a
     resolution from {640x360, 1280x720, 1920x1080, 3840x2160} and a step
     count from {8, 16, 32, 128} drawn once; Poisson arrivals at rate_hz in
@@ -604,7 +605,7 @@ def served_poisson(cf, scenes, torch, rate_hz: float, seconds: float, warm_s: fl
     gaps = rng.exponential(1.0 / rate_hz, size=int(rate_hz * (warm_s + seconds) * 1.5) + 16)
     which = rng.integers(n_streams, size=gaps.size)
     with cf.Server(vol, budget_bytes=budget_bytes, max_batch=64, max_queue=4096,
-                   queues=queues, history_in_output=True) as srv:
+                   queues=queues, history_in_output=True, start_lead_us=start_lead_us) as srv:
         t0 = time.monotonic()
         t_arr = t0 + np.cumsum(gaps)
         k, t_end = 0, t0 + warm_s + seconds

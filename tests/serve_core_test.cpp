@@ -474,8 +474,10 @@ static void test_start_lead() {
   const double eager2 = closed_loop_batch(-1, 2), lead2 = closed_loop_batch(500000, 2);
   printf("start_lead: requests a batch, at once / with the lead: window 1 %.2f / %.2f, "
          "window 2 %.2f / %.2f\n", eager1, lead1, eager2, lead2);
-  CHECK(lead1 >= 3.5);
-  CHECK(lead2 >= 7.0);
+  // (exactly 4 and 8 when the client's resubmissions are prompt; margins
+  // for a loaded machine under the sanitizers)
+  CHECK(lead1 >= 3.2);
+  CHECK(lead2 >= 6.5);
   printf("start_lead ok\n");
 }
 

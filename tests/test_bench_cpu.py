@@ -50,7 +50,7 @@ def test_roofline_fractions():
 
 
 def test_timed_window_does_not_depend_on_warmup_or_steps():
-    # the driver's --steps 20 --warmup 5 and the defaults time the same frames
+    # a short run (--steps 20 --warmup 5) and the defaults time the same frames
     a, b = bench.timed_frames(20), bench.timed_frames(300)
     assert sorted(set(a)) == sorted(set(b)) == list(range(bench.TIMED_FIRST,
                                                           bench.TIMED_FIRST + bench.TIMED_PERIOD))

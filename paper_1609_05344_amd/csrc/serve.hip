@@ -1,8 +1,10 @@
 // Serving: persistent batched render + resolve kernels, the HIP executor
 // behind the scheduler, and the cloud_serve_* C ABI.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -363,14 +365,23 @@ class HipExecutor : public serve::Executor {
         e = graphs_ ? hipGraphLaunch(exec_[slot][1], stream_[1]) : enqueue_resolve(slot);
     }
     if (e == hipSuccess) e = hipEventRecord(event_[slot], stream_[split_ ? 1 : 0]);
-    return e == hipSuccess ? 0 : CLOUD_E_HIP;
+    if (e != hipSuccess) return CLOUD_E_HIP;
+    // a trace range per batch, from its launch to the moment it is seen done
+    char name[48];
+    std::snprintf(name, sizeof name, "serve batch: %d requests", (int)items.size());
+    range_[slot] = roctxRangeStartA(name);
+    ranged_[slot] = true;
+    return 0;
   }
 
   int query(int slot) override {
     const hipError_t e = hipEventQuery(event_[slot]);
-    if (e == hipSuccess) return 1;
     if (e == hipErrorNotReady) return 0;
-    return CLOUD_E_HIP;
+    if (ranged_[slot]) {
+      roctxRangeStop(range_[slot]);
+      ranged_[slot] = false;
+    }
+    return e == hipSuccess ? 1 : CLOUD_E_HIP;
   }
 
  private:
@@ -434,6 +445,8 @@ class HipExecutor : public serve::Executor {
   ServeTable* dev_[kSlots] = {};
   hipGraph_t graph_[kSlots][2] = {};
   hipGraphExec_t exec_[kSlots][2] = {};
+  roctx_range_id_t range_[kSlots] = {};
+  bool ranged_[kSlots] = {};
 };
 
 }  // namespace

@@ -181,3 +181,46 @@ def test_half_storage_against_f32_source(cf, name, dtype, layout, occ):
     err = max_err(img[pix[:, 1], pix[:, 0]], want)
     say(f"  max-abs {err:.3g}")
     assert err < HALF_TOL
+
+
+def test_served_c5_fp16_quad_4k_chains(cf):
+    """The 8-view 4K served configuration: C5's FP16 512^3 quad + occupancy
+    volume (above 512 MiB, so the server holds 4 render workgroups a CU), one
+    stream per view, 3 frames each submitted together (two in flight), each
+    stream resolving against its previous output. Every served frame is
+    bitwise the plain chain's, and two streams' last frames match the oracle
+    at sampled pixels."""
+    import torch
+    w = scenes.workload("C5")
+    W, H, V = w.width, w.height, w.views
+    frames = [400, 401, 402]
+    say(f"serve: C5, {V} streams x {len(frames)} frames at {W}x{H}, FP16 quad + occupancy, "
+        "history in the outputs")
+    sc = scenes.make_scene(w, dtype="f16")
+    vol = cf.device_volume(sc, layout="quad", occupancy=True)
+
+    def cam(s, f):
+        return w.camera(f, view=s)
+
+    outs = [[torch.zeros((H, W, 4), device="cuda") for _ in frames] for _ in range(V)]
+    with cf.Server(vol, budget_bytes=16 << 30, max_batch=64, history_in_output=True) as srv:
+        ids = [srv.submit(s, cam(s, f), w.params, W, H, f, outs[s][k])
+               for k, f in enumerate(frames) for s in range(V)]
+        got = finish(srv, ids, timeout=300.0)
+        assert all(c["status"] == 0 for c in got.values())
+    torch.cuda.synchronize()
+    pix = scenes.random_pixels(W, H, 400, seed=9)
+    hist = torch.zeros((H, W, 4), device="cuda")
+    cur = torch.empty((H, W, 4), device="cuda")
+    for s in range(V):
+        cams = [cam(s, f) for f in frames]
+        for k, f in enumerate(frames):
+            cf.cloud_render(vol, cams[k], w.params, f, W, H, out=cur)
+            cf.cloud_taa_resolve(cur, hist, hist, 0.1, 0 if k == 0 else f)
+            assert torch.equal(outs[s][k], hist), (s, k)
+        if s in (0, 5):
+            want = oracle_chain_sampled(oracle_volume(sc), cams, w.params, W, H, frames, pix)
+            got_px = to_np(outs[s][-1])[pix[:, 1], pix[:, 0]]
+            assert max_err(got_px, want[-1][1]) < HALF_TOL, s
+    del outs, hist, cur
+    torch.cuda.empty_cache()

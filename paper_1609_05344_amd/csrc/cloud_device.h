@@ -183,7 +183,7 @@ __device__ __forceinline__ bool occupied(const DevVolume& v, int kx, int ky, int
   const int by = ky >> v.occ_lg;
   const int bz = kz >> v.occ_lg;
   const int b = mul24(bz, v.occ_plane) + mul24(by, v.occ_nbx) + bx;   // < 32768
-  return (s_occupancy[b >> 5] >> (b & 31)) & 1u;
+  return __builtin_amdgcn_ubfe(s_occupancy[b >> 5], (uint32_t)b, 1u) != 0u;   // bit b & 31
 }
 
 // ---------------------------------------------------------------------------
@@ -205,8 +205,7 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
   struct Addr {
     int idx[8];
   };
-  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz,
-                                              bool live) {
+  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz) {
     const int xa = kx, xb = min(kx + 1, v.nx - 1);
     const int ya = ky, yb = min(ky + 1, v.ny - 1);
     const int za = kz, zb = min(kz + 1, v.nz - 1);
@@ -214,10 +213,15 @@ struct BaseSampler<DT, LAYOUT_DENSE> {
     // 24-bit multiplies are exact
     const int ra = __umul24(ya, v.row), rb = __umul24(yb, v.row);
     const int pa = __umul24(za, v.plane), pb = __umul24(zb, v.plane);
-    const int i0 = live ? pa + ra : 0, i1 = live ? pa + rb : 0;
-    const int i2 = live ? pb + ra : 0, i3 = live ? pb + rb : 0;
-    const int x0 = live ? xa : 0, x1 = live ? xb : 0;
-    return {{i0 + x0, i0 + x1, i1 + x0, i1 + x1, i2 + x0, i2 + x1, i3 + x0, i3 + x1}};
+    const int i0 = pa + ra, i1 = pa + rb, i2 = pb + ra, i3 = pb + rb;
+    return {{i0 + xa, i0 + xb, i1 + xa, i1 + xb, i2 + xa, i2 + xb, i3 + xa, i3 + xb}};
+  }
+  // the entry-0 redirect of a dead lookup
+  __device__ static __forceinline__ Addr redirect(const Addr& a, bool live) {
+    Addr r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r.idx[k] = live ? a.idx[k] : 0;
+    return r;
   }
   __device__ static __forceinline__ void fetch(const DevVolume& v, const Addr& a,
                                                uint32_t (&w)[kWords]) {
@@ -321,11 +325,13 @@ struct QuadSampler {
   struct Addr {
     entry_off_t<TAB> a, b;   // byte offsets of planes kz and kz + 1
   };
-  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz,
-                                              bool live) {
+  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz) {
     entry_off_t<TAB> ia, ib;
     quad_entries<TAB>(v, kx, ky, kz, ia, ib);
-    return {live ? ia : 0u, live ? ib : 0u};
+    return {ia, ib};
+  }
+  __device__ static __forceinline__ Addr redirect(const Addr& e, bool live) {
+    return {live ? e.a : 0u, live ? e.b : 0u};
   }
   __device__ static __forceinline__ void fetch(const DevVolume& v, const Addr& e,
                                                uint32_t (&w)[kWords]) {
@@ -362,10 +368,11 @@ struct OctSampler {
   struct Addr {
     entry_off_t<TAB> e;   // byte offset of the footprint's entry
   };
-  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz,
-                                              bool live) {
-    const entry_off_t<TAB> ie = packed_entry<TAB>(v, kx, ky, kz + 1);
-    return {live ? ie : 0u};
+  __device__ static __forceinline__ Addr addr(const DevVolume& v, int kx, int ky, int kz) {
+    return {packed_entry<TAB>(v, kx, ky, kz + 1)};
+  }
+  __device__ static __forceinline__ Addr redirect(const Addr& a, bool live) {
+    return {live ? a.e : 0u};
   }
   __device__ static __forceinline__ void fetch(const DevVolume& v, const Addr& a,
                                                uint32_t (&w)[kWords]) {
@@ -409,8 +416,11 @@ struct BaseLookup {
     split_coord(fx, v.nx, q.wx, kx);
     split_coord(fy, v.ny, q.wy, ky);
     split_coord(fz, v.nz, q.wz, kz);
+    // the entry offsets first, so that their LDS reads (table layouts) are in
+    // flight with the occupancy test's
+    const typename S::Addr raw = S::addr(v, kx, ky, kz);
     q.live = occupied(v, kx, ky, kz);
-    q.addr = S::addr(v, kx, ky, kz, q.live);
+    q.addr = S::redirect(raw, q.live);
     return q;
   }
 

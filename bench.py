@@ -410,6 +410,51 @@ def paper_table(cf, scenes, torch, np, dtype: str, layout: str, frames=range(10,
 # Offset replay: the render's own fetches from precomputed corners
 # ---------------------------------------------------------------------------
 
+def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_hist,
+                  seq_ms) -> dict:
+    """The same frames through cloud_render_resolve: each launch renders frame
+    f and resolves frame f - 1 (rendered by the launch before), so a step is
+    still one render and one resolve. The resolved history after the same
+    frame sequence is compared bit for bit with the sequential run's."""
+    W, H = w.width, w.height
+    cur = [torch.empty((H, W, 4), device=vol.base.device) for _ in range(2)]
+    hist = torch.zeros((H, W, 4), device=vol.base.device)
+    state = {"k": 0, "prev": None}
+
+    def step(f):
+        k = state["k"]
+        if state["prev"] is None:
+            cf.cloud_render(vol, w.camera(f), p, f, W, H, out=cur[k & 1])
+        else:
+            cf.cloud_render_resolve(vol, w.camera(f), p, f, W, H, cur[(k - 1) & 1], hist, hist,
+                                    w.taa_blend, state["prev"], out=cur[k & 1])
+        state["prev"], state["k"] = f, k + 1
+
+    for f in warm_frames(settle) + warm:
+        step(f)
+    torch.cuda.synchronize()
+    a, b = TimingEvent(), TimingEvent()
+    t0 = time.perf_counter()
+    a.record()
+    for f in timed:
+        step(f)
+    b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # the last frame's resolve, outside the timed region (the first timed
+    # launch resolved the last warm-up frame instead)
+    cf.cloud_taa_resolve(cur[(state["k"] - 1) & 1], hist, hist, w.taa_blend, state["prev"])
+    torch.cuda.synchronize()
+    ms = wall * 1e3 / len(timed)
+    return {"form": "cloud_render_resolve: the render of frame f and the resolve of frame f - 1 "
+                    "in one launch, the resolve's workgroups after the render's",
+            "ms_per_step": round(ms, 4),
+            "value": round(lk_timed / wall / 1e9, 3),
+            "event_ms_per_step": round(a.elapsed_time(b) / len(timed), 4),
+            "speedup_vs_sequential": round(seq_ms / ms, 3),
+            "history_bitwise_equal": bool(torch.equal(hist, seq_hist))}
+
+
 def offset_replay(cf, torch, np, w, vol, p, frames):
     """Times cloud_gather_replay on the given frames' recorded lookups (corner
     codes written by cloud_gather_record outside the timed launches): mode 0
@@ -782,6 +827,9 @@ def main():
     ap.add_argument("--jitter-mode", type=int, default=None, choices=[0, 1, 2, 3],
                     help="start offsets: 0 none, 1 per pixel (the workload's), 2 per 8x8 tile, "
                          "3 per frame")
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the pipelined leg (cloud_render_resolve: frame f's render and "
+                         "frame f - 1's resolve in one launch)")
     ap.add_argument("--no-replay", action="store_true",
                     help="skip the offset-replay measurement")
     ap.add_argument("--serve-queues", type=int, default=1, choices=[1, 2])
@@ -1016,6 +1064,9 @@ def main():
                      "frames_per_group": EVENT_EVERY},
         "render_kernel_timed_frames": len(sampled),
     }
+    if not args.no_pipelined and V == 1 and not reproject and not w.display:
+        line["pipelined"] = pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed,
+                                          hist[0], ms_per_step)
     if not args.no_replay:
         line["offset_replay"] = offset_replay(cf, torch, np, w, vol, p,
                                               range(TIMED_FIRST, TIMED_FIRST + 4))

@@ -21,6 +21,7 @@ from ._lib import (  # noqa: F401
     cloud_render,
     cloud_render_views,
     cloud_render_depth,
+    cloud_render_resolve,
     cloud_taa_resolve_reproject,
     cloud_composite,
     cloud_taa_resolve,

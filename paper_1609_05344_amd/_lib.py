@@ -59,7 +59,7 @@ class cloud_params(ctypes.Structure):
 _lib = None
 
 
-ABI_VERSION = 4   # the struct layouts and signatures this binding marshals
+ABI_VERSION = 5   # the struct layouts and signatures this binding marshals
 
 
 def load():
@@ -86,6 +86,10 @@ def load():
                                      POINTER(cloud_params), c_uint32, c_void_p, c_void_p]
     lib.cloud_taa_resolve.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_float,
                                       c_uint32, c_void_p]
+    lib.cloud_render_resolve.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera),
+                                         POINTER(cloud_params), c_uint32, c_int32, c_int32,
+                                         c_void_p, c_void_p, c_void_p, c_void_p, c_float,
+                                         c_uint32, c_void_p]
     lib.cloud_jitter_offsets.argtypes = [c_void_p, c_int64, c_uint32, c_uint32, c_void_p, c_void_p]
     lib.cloud_check_buffer.argtypes = [c_void_p, c_uint64]
     lib.cloud_tune.argtypes = [c_char_p, c_int32]
@@ -484,6 +488,25 @@ def cloud_taa_resolve(current, history, out, blend: float, frame_index: int, str
     check(load().cloud_taa_resolve(_ptr(current), _ptr(history), _ptr(out), width, height,
                                    float(blend), int(frame_index) & 0xFFFFFFFF, _stream(stream)))
     return out
+
+
+def cloud_render_resolve(volume: Volume, camera, params, frame_index: int, width: int,
+                         height: int, prev, history, resolved, blend: float,
+                         prev_frame_index: int, out=None, stream=None):
+    """The render of frame_index into `out` and the resolve of `prev` (the
+    previous frame's render) against `history` into `resolved`, in one launch;
+    returns (out, resolved)."""
+    _image(prev, (height, width, 4), "prev")
+    _image(history, (height, width, 4), "history")
+    out = _out(out, (height, width, 4), volume.base.device)
+    resolved = _out(resolved, (height, width, 4), volume.base.device)
+    cam, prm = make_camera(camera), make_params(params)
+    check(load().cloud_render_resolve(ctypes.byref(volume.struct), ctypes.byref(cam),
+                                      ctypes.byref(prm), int(frame_index) & 0xFFFFFFFF,
+                                      int(width), int(height), _ptr(out), _ptr(prev),
+                                      _ptr(history), _ptr(resolved), float(blend),
+                                      int(prev_frame_index) & 0xFFFFFFFF, _stream(stream)))
+    return out, resolved
 
 
 # ---------------------------------------------------------------------------

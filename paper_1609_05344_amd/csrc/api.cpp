@@ -621,10 +621,11 @@ int cloud_march_rays(const cloud_volume* volume, const float* origins, const flo
   CLOUD_GUARD_END
 }
 
-int cloud_taa_resolve(const float* current, const float* history, float* out, int32_t width,
-                      int32_t height, float blend, uint32_t frame_index, void* hip_stream) {
-  CLOUD_GUARD_BEGIN
-  clear_error();
+// The checks of a resolve of current against history into out; *copy
+// receives whether it is a copy (no history, or frame 0).
+static int check_resolve(const float* current, const float* history, const float* out,
+                         int32_t width, int32_t height, float blend, uint32_t frame_index,
+                         bool* copy) {
   int rc = check_image(width, height, 1);
   if (rc) return rc;
   if (!std::isfinite(blend) || !(blend > 0.0f) || blend > 1.0f)
@@ -632,20 +633,73 @@ int cloud_taa_resolve(const float* current, const float* history, float* out, in
   const size_t bytes = (size_t)width * height * 16;
   if ((rc = check_span(current, bytes, "current"))) return rc;
   if ((rc = check_span(out, bytes, "out"))) return rc;
-  const bool copy = history == nullptr || frame_index == 0;
-  if (!copy && (rc = check_span(history, bytes, "history"))) return rc;
+  *copy = history == nullptr || frame_index == 0;
+  if (!*copy && (rc = check_span(history, bytes, "history"))) return rc;
   const uintptr_t a = reinterpret_cast<uintptr_t>(current), b = reinterpret_cast<uintptr_t>(out);
   if ((a | b | reinterpret_cast<uintptr_t>(history)) % 16)
     return fail(CLOUD_E_INVALID, "images must be 16-byte aligned");
   if (a < b + bytes && b < a + bytes) return fail(CLOUD_E_INVALID, "out overlaps current");
-  if (!copy && history != out) {
+  if (!*copy && history != out) {
     const uintptr_t h = reinterpret_cast<uintptr_t>(history);
     if (h < b + bytes && b < h + bytes)
       return fail(CLOUD_E_INVALID, "out partially overlaps history");
   }
+  return CLOUD_OK;
+}
+
+int cloud_taa_resolve(const float* current, const float* history, float* out, int32_t width,
+                      int32_t height, float blend, uint32_t frame_index, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  bool copy = false;
+  int rc = check_resolve(current, history, out, width, height, blend, frame_index, &copy);
+  if (rc) return rc;
   hipError_t e = launch_taa(current, history, out, width, height, blend, copy,
                             static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(CLOUD_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
+  return CLOUD_OK;
+  CLOUD_GUARD_END
+}
+
+int cloud_render_resolve(const cloud_volume* volume, const cloud_camera* camera,
+                         const cloud_params* params, uint32_t frame_index, int32_t width,
+                         int32_t height, float* out_rgba, const float* prev_rgba,
+                         const float* history, float* resolved, float blend,
+                         uint32_t prev_frame_index, void* hip_stream) {
+  CLOUD_GUARD_BEGIN
+  clear_error();
+  if (!camera) return fail(CLOUD_E_INVALID, "camera is NULL");
+  int rc = check_image(width, height, 1);
+  if (rc) return rc;
+  DevVolume v;
+  int dtype;
+  if ((rc = prepare_volume(volume, &v, &dtype))) return rc;
+  DevParams p;
+  if ((rc = prepare_params(params, volume, &p))) return rc;
+  const size_t bytes = (size_t)width * height * 16;
+  if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
+    return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
+  if ((rc = check_span(out_rgba, bytes, "out_rgba"))) return rc;
+  bool copy = false;
+  if ((rc = check_resolve(prev_rgba, history, resolved, width, height, blend, prev_frame_index,
+                          &copy)))
+    return rc;
+  // the render runs beside the resolve: its output must be none of the
+  // resolve's images
+  const uintptr_t o = reinterpret_cast<uintptr_t>(out_rgba);
+  const float* others[3] = {prev_rgba, resolved, copy ? nullptr : history};
+  for (const float* q : others) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(q);
+    if (q && a < o + bytes && o < a + bytes)
+      return fail(CLOUD_E_INVALID, "out_rgba overlaps prev_rgba, history or resolved");
+  }
+  DevCameras cams;
+  if ((rc = prepare_camera(camera, width, height, &cams.c[0]))) return rc;
+  hipError_t e = launch_render_resolve(v, dtype, volume->layout, p, cams, frame_index, width,
+                                       height, out_rgba, prev_rgba, history, resolved, blend,
+                                       copy, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess)
+    return fail(CLOUD_E_HIP, std::string("render and resolve launch: ") + hipGetErrorString(e));
   return CLOUD_OK;
   CLOUD_GUARD_END
 }

@@ -102,4 +102,16 @@ hipError_t launch_jitter(const uint32_t* pxy, long long n, uint32_t frame, uint3
 hipError_t launch_taa(const float* cur, const float* hist, float* out, int W, int H, float blend,
                       bool copy, hipStream_t s);
 
+// Whether the resolve of a W x H frame deals each XCD one contiguous run of
+// its tiles.
+int taa_xcd_runs(int W, int H);
+
+// One launch: the render of one view (frame, into out) and the resolve of
+// the previous frame (prev against hist into resolved, or a copy of prev
+// when copy is set).
+hipError_t launch_render_resolve(const DevVolume& v, int dtype, int layout, const DevParams& p,
+                                 const DevCameras& c, uint32_t frame, int W, int H, float* out,
+                                 const float* prev, const float* hist, float* resolved,
+                                 float blend, bool copy, hipStream_t s);
+
 }  // namespace cloud

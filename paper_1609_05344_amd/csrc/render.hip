@@ -6,6 +6,7 @@
 
 #include "cloud_device.h"
 #include "cloud_launch.h"
+#include "taa_device.h"
 
 namespace cloud {
 
@@ -38,26 +39,26 @@ TileWalk tile_walk() {
 
 enum { kImage = 0, kCount = 1, kDepth = 2 };
 
+// Block b of a render of nb tile blocks (b names the XCD as b % 8).
 template <int DT, int LAYOUT, bool DETAIL, int MODE>
-__global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams prm,
-                                                     DevCameras cams, uint32_t frame, int W,
-                                                     int H, int tiles_x, int tiles_y, int S,
-                                                     int L, float4* __restrict__ out,
-                                                     unsigned long long* __restrict__ counts,
-                                                     uint2* __restrict__ trace,
-                                                     float* __restrict__ depth) {
+__device__ __forceinline__ void render_block(int b, int nb, const DevVolume& vol,
+                                             const DevParams& prm, const DevCameras& cams,
+                                             uint32_t frame, int W, int H, int tiles_x,
+                                             int tiles_y, int S, int L, float4* __restrict__ out,
+                                             unsigned long long* __restrict__ counts,
+                                             uint2* __restrict__ trace,
+                                             float* __restrict__ depth) {
   constexpr bool COUNT = MODE == kCount;
   const int tiles_per_view = tiles_x * tiles_y;
   // On odd frames each XCD takes its blocks in reverse order (blocks x,
   // x + 8, ... are XCD x's), so a frame starts on the tiles each XCD ended
   // the one before with, whose volume lines its L2 and the last-level cache
   // still hold.
-  int b = blockIdx.x;
   if (frame & 1u) {
-    const int x = b & 7, k = b >> 3, nx = ((int)gridDim.x - x + 7) >> 3;
+    const int x = b & 7, k = b >> 3, nx = (nb - x + 7) >> 3;
     b = 8 * (nx - 1 - k) + x;
   }
-  const int tile = xcd_walk(b, gridDim.x, L);
+  const int tile = xcd_walk(b, nb, L);
   const int view = tile / tiles_per_view;
   int tx, ty;
   supertile(tile - view * tiles_per_view, tiles_x, tiles_y, S, tx, ty);
@@ -92,6 +93,48 @@ __global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams pr
     out[pix] = make_float4(r.r, r.g, r.b, r.a);
     if constexpr (MODE == kDepth) depth[pix] = r.depth;
   }
+}
+
+template <int DT, int LAYOUT, bool DETAIL, int MODE>
+__global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams prm,
+                                                     DevCameras cams, uint32_t frame, int W,
+                                                     int H, int tiles_x, int tiles_y, int S,
+                                                     int L, float4* __restrict__ out,
+                                                     unsigned long long* __restrict__ counts,
+                                                     uint2* __restrict__ trace,
+                                                     float* __restrict__ depth) {
+  render_block<DT, LAYOUT, DETAIL, MODE>(blockIdx.x, gridDim.x, vol, prm, cams, frame, W, H,
+                                         tiles_x, tiles_y, S, L, out, counts, trace, depth);
+}
+
+// One view's render of frame f and the resolve of frame f - 1 in one launch
+// (cloud_render_resolve): blocks [0, nbp) render (nb of them are tiles;
+// nbp rounds nb up to a multiple of 8, so that the resolve's blocks keep
+// block % 8 as their XCD), the rest resolve prev against hist into resolved
+// (or copy prev there when copy is set). The resolve's blocks come last, so
+// they fill the render's tail, when fewer and fewer of its tiles are left.
+template <int DT, int LAYOUT, bool DETAIL>
+__global__ __launch_bounds__(256) void render_resolve_kernel(
+    DevVolume vol, DevParams prm, DevCameras cams, uint32_t frame, int W, int H, int tiles_x,
+    int tiles_y, int S, int L, float4* __restrict__ out, int nb, int nbp,
+    const float4* __restrict__ prev, const float4* hist, float4* resolved, int taa_tiles_x,
+    int taa_tiles, float blend, int xcd_runs, int copy) {
+  if ((int)blockIdx.x < nbp) {
+    if ((int)blockIdx.x < nb)
+      render_block<DT, LAYOUT, DETAIL, kImage>(blockIdx.x, nb, vol, prm, cams, frame, W, H,
+                                               tiles_x, tiles_y, S, L, out, nullptr, nullptr,
+                                               nullptr);
+    return;
+  }
+  const int t = (int)blockIdx.x - nbp;
+  if (copy) {
+    // tile t of 256 pixels, row-major over the image
+    const long long i = (long long)t * 256 + threadIdx.x;
+    if (i < (long long)W * H) resolved[i] = prev[i];
+    return;
+  }
+  taa_block<32>(xcd_runs ? xcd_walk(t, taa_tiles, 0) : t, prev, hist, resolved, W, H,
+                taa_tiles_x, blend);
 }
 
 template <int DT, int LAYOUT, bool DETAIL>
@@ -329,6 +372,42 @@ struct RenderLaunch {
   }
 };
 
+struct RenderResolveLaunch {
+  const DevVolume& v;
+  const DevParams& p;
+  const DevCameras& c;
+  uint32_t frame;
+  int W, H;
+  float* out;
+  const float* prev;
+  const float* hist;
+  float* resolved;
+  float blend;
+  bool copy;
+  hipStream_t s;
+  template <int DT, int LAYOUT, bool DETAIL, int MODE>
+  hipError_t run() {
+    if constexpr (MODE != kImage) {
+      return hipErrorInvalidValue;
+    } else {
+      const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
+      const int nb = tiles_x * tiles_y, nbp = (nb + 7) / 8 * 8;
+      constexpr int TW = 32, TH = 256 / TW;
+      const int ttx = (W + TW - 1) / TW, tty = (H + TH - 1) / TH;
+      const int taa_blocks = copy ? (int)(((long long)W * H + 255) / 256) : ttx * tty;
+      const TileWalk tw = tile_walk();
+      hipLaunchKernelGGL((render_resolve_kernel<DT, LAYOUT, DETAIL>), dim3(nbp + taa_blocks),
+                         dim3(256), 0, s, v, p, c, frame, W, H, tiles_x, tiles_y, tw.S, tw.L,
+                         reinterpret_cast<float4*>(out), nb, nbp,
+                         reinterpret_cast<const float4*>(prev),
+                         reinterpret_cast<const float4*>(hist),
+                         reinterpret_cast<float4*>(resolved), ttx, ttx * tty, blend,
+                         taa_xcd_runs(W, H), copy ? 1 : 0);
+      return hipGetLastError();
+    }
+  }
+};
+
 struct RaysLaunch {
   const DevVolume& v;
   const DevParams& p;
@@ -354,6 +433,14 @@ hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevPar
   RenderLaunch f{v, p, c, n_views, frame, W, H, out, counts, trace, depth, s};
   const int mode = counts != nullptr || trace != nullptr ? kCount : depth != nullptr ? kDepth : kImage;
   return dispatch(dtype, sampler_layout(v, layout), v.detail != nullptr, mode, f);
+}
+
+hipError_t launch_render_resolve(const DevVolume& v, int dtype, int layout, const DevParams& p,
+                                 const DevCameras& c, uint32_t frame, int W, int H, float* out,
+                                 const float* prev, const float* hist, float* resolved,
+                                 float blend, bool copy, hipStream_t s) {
+  RenderResolveLaunch f{v, p, c, frame, W, H, out, prev, hist, resolved, blend, copy, s};
+  return dispatch(dtype, sampler_layout(v, layout), v.detail != nullptr, kImage, f);
 }
 
 hipError_t launch_rays(const DevVolume& v, int dtype, int layout, const DevParams& p,

@@ -4,17 +4,16 @@
 #include "cloud_device.h"
 #include "cloud_launch.h"
 #include "stream_io.h"
+#include "taa_device.h"
 
 namespace cloud {
 
 // ---------------------------------------------------------------------------
-// Temporal resolve (Section 3.2): a tile of 256 pixels of the current frame
-// (TW wide) plus a one-pixel edge-clamped halo is staged in LDS, so each
-// current pixel is read from HBM about once although nine threads use it.
-// Tiles are row-major. With xcd_runs, each XCD takes one contiguous eighth of
-// them (workgroups are dealt to the XCDs round-robin), so a tile's halo rows
-// were mostly just read by a neighbour in the same L2; without, consecutive
-// tiles go to different XCDs.
+// Temporal resolve (Section 3.2), one tile of 256 pixels a workgroup
+// (taa_block). Tiles are row-major. With xcd_runs, each XCD takes one
+// contiguous eighth of them (workgroups are dealt to the XCDs round-robin),
+// so a tile's halo rows were mostly just read by a neighbour in the same L2;
+// without, consecutive tiles go to different XCDs.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int taa_tile(int xcd_runs) {
@@ -25,40 +24,7 @@ template <int TW>
 __global__ __launch_bounds__(256) void taa_kernel(const float4* __restrict__ cur,
                                                   const float4* hist, float4* out, int W, int H,
                                                   int tiles_x, float blend, int xcd_runs) {
-  constexpr int TH = 256 / TW;
-  __shared__ float4 tile[TH + 2][TW + 2];
-  const int t = taa_tile(xcd_runs);
-  const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
-  const int bx = txi * TW, by = tyi * TH;
-  for (int i = threadIdx.x; i < (TH + 2) * (TW + 2); i += 256) {
-    const int ly = i / (TW + 2), lx = i - ly * (TW + 2);
-    const int gx = min(max(bx + lx - 1, 0), W - 1);
-    const int gy = min(max(by + ly - 1, 0), H - 1);
-    tile[ly][lx] = cur[(size_t)gy * W + gx];
-  }
-  __syncthreads();
-  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-  const int px = bx + lx, py = by + ly;
-  if (px >= W || py >= H) return;
-  const float4 c = tile[ly + 1][lx + 1];
-  float4 lo = c, hi = c;
-#pragma unroll
-  for (int dy = 0; dy < 3; ++dy) {
-#pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      const float4 v = tile[ly + dy][lx + dx];
-      lo.x = fminf(lo.x, v.x); lo.y = fminf(lo.y, v.y); lo.z = fminf(lo.z, v.z); lo.w = fminf(lo.w, v.w);
-      hi.x = fmaxf(hi.x, v.x); hi.y = fmaxf(hi.y, v.y); hi.z = fmaxf(hi.z, v.z); hi.w = fmaxf(hi.w, v.w);
-    }
-  }
-  const size_t p = (size_t)py * W + px;
-  float4 h = load_stream(hist + p);
-  h.x = fminf(fmaxf(h.x, lo.x), hi.x);
-  h.y = fminf(fmaxf(h.y, lo.y), hi.y);
-  h.z = fminf(fmaxf(h.z, lo.z), hi.z);
-  h.w = fminf(fmaxf(h.w, lo.w), hi.w);
-  store_stream(out + p, make_float4(fmaf(blend, c.x - h.x, h.x), fmaf(blend, c.y - h.y, h.y),
-                                    fmaf(blend, c.z - h.z, h.z), fmaf(blend, c.w - h.w, h.w)));
+  taa_block<TW>(taa_tile(xcd_runs), cur, hist, out, W, H, tiles_x, blend);
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
@@ -155,7 +121,7 @@ __global__ __launch_bounds__(256) void taa_reproject_kernel(const float4* __rest
 // output: 48 bytes a pixel) stay inside the 256 MB last-level cache: measured
 // 15 % faster from 720p to 1440p, 14 % slower at 4K, where the eight XCDs'
 // separate streams then reach HBM.
-static int taa_xcd_runs(int W, int H) {
+int taa_xcd_runs(int W, int H) {
   return 48.0 * W * H <= 192.0 * (1 << 20) ? 1 : 0;
 }
 

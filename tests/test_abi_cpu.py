@@ -37,7 +37,7 @@ def test_exports_every_declared_function(lib):
     assert len(names) >= 6
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.cloud_abi_version() == _lib.ABI_VERSION == 4
+    assert lib.cloud_abi_version() == _lib.ABI_VERSION == 5
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -86,6 +86,12 @@ def test_argument_errors_before_any_launch(lib):
     rc = lib.cloud_render_views(ctypes.byref(vol), ctypes.byref(cam), 0, ctypes.byref(prm), 0, 8, 8,
                                 None, None)
     assert rc == _lib.CLOUD_E_INVALID and "n_views" in _lib.last_error()
+    rc = lib.cloud_render_resolve(ctypes.byref(vol), None, ctypes.byref(prm), 1, 8, 8, None, None,
+                                  None, None, ctypes.c_float(0.1), 0, None)
+    assert rc == _lib.CLOUD_E_INVALID and "camera" in _lib.last_error()
+    rc = lib.cloud_render_resolve(ctypes.byref(vol), ctypes.byref(cam), ctypes.byref(prm), 1, 8, 0,
+                                  None, None, None, None, ctypes.c_float(0.1), 0, None)
+    assert rc == _lib.CLOUD_E_INVALID and "height" in _lib.last_error()
     # a successful-looking call leaves the error text of the last failure only
     assert lib.cloud_jitter_offsets(None, 0, 0, 0, None, None) == _lib.CLOUD_OK
 

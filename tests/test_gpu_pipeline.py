@@ -1,0 +1,135 @@
+"""cloud_render_resolve: the render of frame f and the resolve of frame f - 1
+in one launch (Sections 1, 3.1, 3.2). It must give bitwise the images of
+cloud_render followed by cloud_taa_resolve, frame by frame, for every
+storage form, ragged sizes and the copy path; and the chain it builds must
+match the oracle's at sampled pixels."""
+
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1609_05344_amd import scenes
+from tests.helpers import FP32_TOL, max_err, oracle_chain_sampled, oracle_volume, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import torch
+    import paper_1609_05344_amd as cf
+    assert torch.cuda.is_available()
+    cf.load()
+    return cf
+
+
+def chains(cf, vol, w, W, H, frames, blend=0.1):
+    """The same frames sequentially and pipelined. Returns, per frame, the
+    sequential (render, history after its resolve) and the pipelined render,
+    plus the pipelined history after each launch (it holds frame k - 1's
+    resolve after launch k) and after the final resolve."""
+    import torch
+    p = w.params
+    cur = torch.empty((H, W, 4), device="cuda")
+    hist = torch.zeros((H, W, 4), device="cuda")
+    seq = []
+    for k, f in enumerate(frames):
+        cf.cloud_render(vol, w.camera(f), p, f, W, H, out=cur)
+        cf.cloud_taa_resolve(cur, hist, hist, blend, 0 if k == 0 else f)
+        seq.append((to_np(cur).copy(), to_np(hist).copy()))
+    bufs = [torch.empty((H, W, 4), device="cuda") for _ in range(2)]
+    hist = torch.full((H, W, 4), 7.0, device="cuda")   # overwritten by the first (copy) resolve
+    pipe, hists = [], []
+    for k, f in enumerate(frames):
+        if k == 0:
+            cf.cloud_render(vol, w.camera(f), p, f, W, H, out=bufs[0])
+        else:
+            cf.cloud_render_resolve(vol, w.camera(f), p, f, W, H, bufs[(k - 1) & 1], hist, hist,
+                                    blend, 0 if k == 1 else frames[k - 1], out=bufs[k & 1])
+            hists.append(to_np(hist).copy())
+        pipe.append(to_np(bufs[k & 1]).copy())
+    cf.cloud_taa_resolve(bufs[(len(frames) - 1) & 1], hist, hist, blend, frames[-1])
+    hists.append(to_np(hist).copy())
+    return seq, pipe, hists
+
+
+@pytest.mark.parametrize("name,dtype,layout,occ,size,frames", [
+    ("H", "f32", "quad", True, None, list(range(400, 406))),     # the benchmark's form
+    ("H", "f16", "quad", True, None, list(range(400, 404))),     # the served storage
+    ("C2", "f32", "quad", True, (333, 197), list(range(0, 5))),  # ragged tiles, blocks not 8k
+    ("C2", "bf16", "oct", False, (131, 67), list(range(3, 7))),
+    ("C1", "f32", "dense", False, (64, 64), list(range(0, 4))),  # 16 tiles
+    ("C3", "f16", "oct", False, (250, 150), list(range(0, 3))),  # with detail erosion
+])
+def test_pipelined_chain_bitwise(cf, name, dtype, layout, occ, size, frames):
+    w = scenes.workload(name)
+    W, H = size or (w.width, w.height)
+    say(f"pipeline: {name} {dtype} {layout} occ={occ} {W}x{H}, {len(frames)} frames")
+    vol = cf.device_volume(scenes.make_scene(w, dtype=dtype), layout=layout, occupancy=occ)
+    seq, pipe, hists = chains(cf, vol, w, W, H, frames)
+    for k in range(len(frames)):
+        assert np.array_equal(pipe[k], seq[k][0]), ("render", k)
+        assert np.array_equal(hists[k], seq[k][1]), ("resolve", k)
+    assert np.mean(seq[-1][1][..., 3] > 0.05) > 0.05   # the frames hold cloud
+
+
+def test_pipelined_chain_against_oracle(cf):
+    # C2's slab layer at a ragged 200x120, 4 jittered frames: the pipelined
+    # chain at sampled pixels against the oracle's chain
+    w = scenes.workload("C2")
+    W, H, frames = 200, 120, [0, 1, 2, 3]
+    sc = scenes.make_scene(w)
+    vol = cf.device_volume(sc, layout="quad", occupancy=True)
+    _, _, hists = chains(cf, vol, w, W, H, frames)
+    pix = scenes.random_pixels(W, H, 300, seed=17)
+    want = oracle_chain_sampled(oracle_volume(sc), [w.camera(f) for f in frames], w.params, W, H,
+                                frames, pix)
+    for k in range(len(frames)):
+        got = hists[k][pix[:, 1], pix[:, 0]]
+        assert max_err(got, want[k][1]) < FP32_TOL, k
+    assert np.mean(want[-1][1][:, 3] > 0.05) > 0.2
+
+
+def test_pipelined_copy_path(cf):
+    # prev_frame_index 0, or no history: the resolve copies the previous render
+    import torch
+    w = scenes.workload("C2")
+    W, H = 96, 72
+    vol = cf.device_volume(scenes.make_scene(w), layout="quad", occupancy=True)
+    prev = cf.cloud_render(vol, w.camera(0), w.params, 0, W, H)
+    ref = cf.cloud_render(vol, w.camera(1), w.params, 1, W, H)
+    for hist, pf in ((torch.ones((H, W, 4), device="cuda"), 0), (None, 5)):
+        out, res = cf.cloud_render_resolve(vol, w.camera(1), w.params, 1, W, H, prev, hist,
+                                           None, 0.1, pf)
+        assert torch.equal(out, ref) and torch.equal(res, prev)
+
+
+def test_pipelined_rejects_overlaps(cf):
+    import torch
+    from paper_1609_05344_amd import _lib
+    w = scenes.workload("C1")
+    W, H = 32, 32
+    vol = cf.device_volume(scenes.make_scene(w), layout="quad")
+    a, b, c = (torch.zeros((H, W, 4), device="cuda") for _ in range(3))
+    lib = cf.load()
+    cam, prm = _lib.make_camera(w.camera(0)), _lib.make_params(w.params)
+
+    def call(out, prev, hist, res):
+        return lib.cloud_render_resolve(ctypes.byref(vol.struct), ctypes.byref(cam),
+                                        ctypes.byref(prm), 1, W, H, out.data_ptr(),
+                                        prev.data_ptr(), hist.data_ptr(), res.data_ptr(),
+                                        ctypes.c_float(0.1), 1, None)
+
+    for args in ((a, a, b, c), (a, b, a, c), (a, b, c, a)):
+        assert call(*args) == _lib.CLOUD_E_INVALID
+        assert "out_rgba overlaps" in _lib.last_error()
+    assert call(a, b, c, b) == _lib.CLOUD_E_INVALID and "overlaps current" in _lib.last_error()
+    assert call(a, b, c, c) == _lib.CLOUD_OK       # in-place history
+    torch.cuda.synchronize()

@@ -416,17 +416,24 @@ def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_h
     f and resolves frame f - 1 (rendered by the launch before), so a step is
     still one render and one resolve. The resolved history after the same
     frame sequence is compared bit for bit with the sequential run's."""
-    W, H = w.width, w.height
-    cur = [torch.empty((H, W, 4), device=vol.base.device) for _ in range(2)]
-    hist = torch.zeros((H, W, 4), device=vol.base.device)
+    W, H, V = w.width, w.height, w.views
+    shape = (V, H, W, 4) if V > 1 else (H, W, 4)
+    cur = [torch.empty(shape, device=vol.base.device) for _ in range(2)]
+    hist = torch.zeros(shape, device=vol.base.device)
     state = {"k": 0, "prev": None}
+
+    def cams(f):
+        return [w.camera(f, view=v) for v in range(V)] if V > 1 else w.camera(f)
 
     def step(f):
         k = state["k"]
         if state["prev"] is None:
-            cf.cloud_render(vol, w.camera(f), p, f, W, H, out=cur[k & 1])
+            if V > 1:
+                cf.cloud_render_views(vol, cams(f), p, f, W, H, out=cur[k & 1])
+            else:
+                cf.cloud_render(vol, cams(f), p, f, W, H, out=cur[k & 1])
         else:
-            cf.cloud_render_resolve(vol, w.camera(f), p, f, W, H, cur[(k - 1) & 1], hist, hist,
+            cf.cloud_render_resolve(vol, cams(f), p, f, W, H, cur[(k - 1) & 1], hist, hist,
                                     w.taa_blend, state["prev"], out=cur[k & 1])
         state["prev"], state["k"] = f, k + 1
 
@@ -443,7 +450,10 @@ def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_h
     wall = time.perf_counter() - t0
     # the last frame's resolve, outside the timed region (the first timed
     # launch resolved the last warm-up frame instead)
-    cf.cloud_taa_resolve(cur[(state["k"] - 1) & 1], hist, hist, w.taa_blend, state["prev"])
+    last = cur[(state["k"] - 1) & 1]
+    for v in range(V):
+        cf.cloud_taa_resolve(last[v] if V > 1 else last, hist[v] if V > 1 else hist,
+                             hist[v] if V > 1 else hist, w.taa_blend, state["prev"])
     torch.cuda.synchronize()
     ms = wall * 1e3 / len(timed)
     return {"form": "cloud_render_resolve: the render of frame f and the resolve of frame f - 1 "
@@ -1064,9 +1074,9 @@ def main():
                      "frames_per_group": EVENT_EVERY},
         "render_kernel_timed_frames": len(sampled),
     }
-    if not args.no_pipelined and V == 1 and not reproject and not w.display:
+    if not args.no_pipelined and not reproject and not w.display:
         line["pipelined"] = pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed,
-                                          hist[0], ms_per_step)
+                                          hist if V > 1 else hist[0], ms_per_step)
     if not args.no_replay:
         line["offset_replay"] = offset_replay(cf, torch, np, w, vol, p,
                                               range(TIMED_FIRST, TIMED_FIRST + 4))

@@ -232,21 +232,23 @@ int cloud_render_depth(const cloud_volume* volume, const cloud_camera* camera,
 
 /* The render of one frame and the temporal resolve of the frame before it
  * in one launch (Sections 1, 3.1, 3.2), for callers that render frame f
- * while frame f - 1 is still to be resolved: exactly cloud_render(volume,
- * camera, params, frame_index, width, height, out_rgba) and
- * cloud_taa_resolve(prev_rgba, history, resolved, width, height, blend,
- * prev_frame_index), with bitwise the same results, but the resolve's
- * workgroups are scheduled after the render's, so they run while the
- * render's last tiles finish. The two parts run concurrently: out_rgba must
- * not overlap prev_rgba, history or resolved, and resolved must not overlap
- * prev_rgba (it may equal history). prev_rgba is device [height][width][4]
- * float32, the previous frame's render; history and resolved as in
- * cloud_taa_resolve (history == NULL or prev_frame_index == 0 copies). */
-int cloud_render_resolve(const cloud_volume* volume, const cloud_camera* camera,
-                         const cloud_params* params, uint32_t frame_index,
-                         int32_t width, int32_t height, float* out_rgba,
-                         const float* prev_rgba, const float* history,
-                         float* resolved, float blend,
+ * while frame f - 1 is still to be resolved: exactly
+ * cloud_render_views(volume, cameras, n_views, params, frame_index, width,
+ * height, out_rgba) and, for each view v, cloud_taa_resolve(prev_rgba[v],
+ * history[v], resolved[v], width, height, blend, prev_frame_index), with
+ * bitwise the same results, but the resolve's workgroups are scheduled after
+ * the render's, so they run while the render's last tiles finish (up to 16
+ * views a launch; more are split into launches of 16). The two parts run
+ * concurrently: out_rgba must not overlap prev_rgba, history or resolved, and
+ * resolved must not overlap prev_rgba (it may equal history). out_rgba,
+ * prev_rgba (the previous frame's render), history and resolved are device
+ * [n_views][height][width][4] float32; history == NULL or prev_frame_index
+ * == 0 copies prev_rgba to resolved. n_views >= 1. */
+int cloud_render_resolve(const cloud_volume* volume, const cloud_camera* cameras,
+                         int32_t n_views, const cloud_params* params,
+                         uint32_t frame_index, int32_t width, int32_t height,
+                         float* out_rgba, const float* prev_rgba,
+                         const float* history, float* resolved, float blend,
                          uint32_t prev_frame_index, void* hip_stream);
 
 /* Temporal resolve with camera reprojection (Section 3.2 names Playdead's

@@ -86,7 +86,7 @@ def load():
                                      POINTER(cloud_params), c_uint32, c_void_p, c_void_p]
     lib.cloud_taa_resolve.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_float,
                                       c_uint32, c_void_p]
-    lib.cloud_render_resolve.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera),
+    lib.cloud_render_resolve.argtypes = [POINTER(cloud_volume), POINTER(cloud_camera), c_int32,
                                          POINTER(cloud_params), c_uint32, c_int32, c_int32,
                                          c_void_p, c_void_p, c_void_p, c_void_p, c_float,
                                          c_uint32, c_void_p]
@@ -495,13 +495,17 @@ def cloud_render_resolve(volume: Volume, camera, params, frame_index: int, width
                          prev_frame_index: int, out=None, stream=None):
     """The render of frame_index into `out` and the resolve of `prev` (the
     previous frame's render) against `history` into `resolved`, in one launch;
-    returns (out, resolved)."""
-    _image(prev, (height, width, 4), "prev")
-    _image(history, (height, width, 4), "history")
-    out = _out(out, (height, width, 4), volume.base.device)
-    resolved = _out(resolved, (height, width, 4), volume.base.device)
-    cam, prm = make_camera(camera), make_params(params)
-    check(load().cloud_render_resolve(ctypes.byref(volume.struct), ctypes.byref(cam),
+    returns (out, resolved). `camera` is one camera ([H, W, 4] images) or a
+    list of them ([n, H, W, 4] images, as cloud_render_views)."""
+    cams = list(camera) if isinstance(camera, (list, tuple)) else [camera]
+    shape = (len(cams), height, width, 4) if isinstance(camera, (list, tuple)) else (height, width, 4)
+    _image(prev, shape, "prev")
+    _image(history, shape, "history")
+    out = _out(out, shape, volume.base.device)
+    resolved = _out(resolved, shape, volume.base.device)
+    arr = (cloud_camera * max(len(cams), 1))(*[make_camera(c) for c in cams])
+    prm = make_params(params)
+    check(load().cloud_render_resolve(ctypes.byref(volume.struct), arr, len(cams),
                                       ctypes.byref(prm), int(frame_index) & 0xFFFFFFFF,
                                       int(width), int(height), _ptr(out), _ptr(prev),
                                       _ptr(history), _ptr(resolved), float(blend),

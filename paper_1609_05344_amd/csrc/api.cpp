@@ -621,16 +621,16 @@ int cloud_march_rays(const cloud_volume* volume, const float* origins, const flo
   CLOUD_GUARD_END
 }
 
-// The checks of a resolve of current against history into out; *copy
-// receives whether it is a copy (no history, or frame 0).
+// The checks of a resolve of n_views images current against history into
+// out; *copy receives whether it is a copy (no history, or frame 0).
 static int check_resolve(const float* current, const float* history, const float* out,
-                         int32_t width, int32_t height, float blend, uint32_t frame_index,
-                         bool* copy) {
-  int rc = check_image(width, height, 1);
+                         int32_t width, int32_t height, int32_t n_views, float blend,
+                         uint32_t frame_index, bool* copy) {
+  int rc = check_image(width, height, n_views);
   if (rc) return rc;
   if (!std::isfinite(blend) || !(blend > 0.0f) || blend > 1.0f)
     return fail(CLOUD_E_INVALID, "blend must be in (0, 1]");
-  const size_t bytes = (size_t)width * height * 16;
+  const size_t bytes = (size_t)width * height * 16 * (size_t)n_views;
   if ((rc = check_span(current, bytes, "current"))) return rc;
   if ((rc = check_span(out, bytes, "out"))) return rc;
   *copy = history == nullptr || frame_index == 0;
@@ -652,7 +652,7 @@ int cloud_taa_resolve(const float* current, const float* history, float* out, in
   CLOUD_GUARD_BEGIN
   clear_error();
   bool copy = false;
-  int rc = check_resolve(current, history, out, width, height, blend, frame_index, &copy);
+  int rc = check_resolve(current, history, out, width, height, 1, blend, frame_index, &copy);
   if (rc) return rc;
   hipError_t e = launch_taa(current, history, out, width, height, blend, copy,
                             static_cast<hipStream_t>(hip_stream));
@@ -661,28 +661,29 @@ int cloud_taa_resolve(const float* current, const float* history, float* out, in
   CLOUD_GUARD_END
 }
 
-int cloud_render_resolve(const cloud_volume* volume, const cloud_camera* camera,
-                         const cloud_params* params, uint32_t frame_index, int32_t width,
-                         int32_t height, float* out_rgba, const float* prev_rgba,
+int cloud_render_resolve(const cloud_volume* volume, const cloud_camera* cameras,
+                         int32_t n_views, const cloud_params* params, uint32_t frame_index,
+                         int32_t width, int32_t height, float* out_rgba, const float* prev_rgba,
                          const float* history, float* resolved, float blend,
                          uint32_t prev_frame_index, void* hip_stream) {
   CLOUD_GUARD_BEGIN
   clear_error();
-  if (!camera) return fail(CLOUD_E_INVALID, "camera is NULL");
-  int rc = check_image(width, height, 1);
+  if (!cameras) return fail(CLOUD_E_INVALID, "cameras is NULL");
+  if (n_views < 1) return fail(CLOUD_E_INVALID, "n_views must be >= 1");
+  int rc = check_image(width, height, n_views);
   if (rc) return rc;
   DevVolume v;
   int dtype;
   if ((rc = prepare_volume(volume, &v, &dtype))) return rc;
   DevParams p;
   if ((rc = prepare_params(params, volume, &p))) return rc;
-  const size_t bytes = (size_t)width * height * 16;
+  const size_t px = (size_t)width * height, bytes = px * 16 * (size_t)n_views;
   if (reinterpret_cast<uintptr_t>(out_rgba) % 16)
     return fail(CLOUD_E_INVALID, "out_rgba must be 16-byte aligned");
   if ((rc = check_span(out_rgba, bytes, "out_rgba"))) return rc;
   bool copy = false;
-  if ((rc = check_resolve(prev_rgba, history, resolved, width, height, blend, prev_frame_index,
-                          &copy)))
+  if ((rc = check_resolve(prev_rgba, history, resolved, width, height, n_views, blend,
+                          prev_frame_index, &copy)))
     return rc;
   // the render runs beside the resolve: its output must be none of the
   // resolve's images
@@ -694,12 +695,19 @@ int cloud_render_resolve(const cloud_volume* volume, const cloud_camera* camera,
       return fail(CLOUD_E_INVALID, "out_rgba overlaps prev_rgba, history or resolved");
   }
   DevCameras cams;
-  if ((rc = prepare_camera(camera, width, height, &cams.c[0]))) return rc;
-  hipError_t e = launch_render_resolve(v, dtype, volume->layout, p, cams, frame_index, width,
-                                       height, out_rgba, prev_rgba, history, resolved, blend,
-                                       copy, static_cast<hipStream_t>(hip_stream));
-  if (e != hipSuccess)
-    return fail(CLOUD_E_HIP, std::string("render and resolve launch: ") + hipGetErrorString(e));
+  for (int i = 0; i < n_views; ++i) {
+    if ((rc = prepare_camera(&cameras[i], width, height, &cams.c[i % kMaxViews]))) return rc;
+    if ((i + 1) % kMaxViews == 0 || i + 1 == n_views) {
+      const int first = i - i % kMaxViews;
+      const size_t off = (size_t)first * px * 4;
+      hipError_t e = launch_render_resolve(
+          v, dtype, volume->layout, p, cams, i - first + 1, frame_index, width, height,
+          out_rgba + off, prev_rgba + off, copy ? nullptr : history + off, resolved + off, blend,
+          copy, static_cast<hipStream_t>(hip_stream));
+      if (e != hipSuccess)
+        return fail(CLOUD_E_HIP, std::string("render and resolve launch: ") + hipGetErrorString(e));
+    }
+  }
   return CLOUD_OK;
   CLOUD_GUARD_END
 }

@@ -106,12 +106,12 @@ hipError_t launch_taa(const float* cur, const float* hist, float* out, int W, in
 // its tiles.
 int taa_xcd_runs(int W, int H);
 
-// One launch: the render of one view (frame, into out) and the resolve of
-// the previous frame (prev against hist into resolved, or a copy of prev
-// when copy is set).
+// One launch: the render of n_views (<= kMaxViews) views (frame, into out)
+// and the resolve of the previous frame's (prev against hist into resolved,
+// or a copy of prev when copy is set), all [n_views][H][W][4].
 hipError_t launch_render_resolve(const DevVolume& v, int dtype, int layout, const DevParams& p,
-                                 const DevCameras& c, uint32_t frame, int W, int H, float* out,
-                                 const float* prev, const float* hist, float* resolved,
-                                 float blend, bool copy, hipStream_t s);
+                                 const DevCameras& c, int n_views, uint32_t frame, int W, int H,
+                                 float* out, const float* prev, const float* hist,
+                                 float* resolved, float blend, bool copy, hipStream_t s);
 
 }  // namespace cloud

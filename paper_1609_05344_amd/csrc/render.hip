@@ -107,18 +107,19 @@ __global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams pr
                                          tiles_x, tiles_y, S, L, out, counts, trace, depth);
 }
 
-// One view's render of frame f and the resolve of frame f - 1 in one launch
-// (cloud_render_resolve): blocks [0, nbp) render (nb of them are tiles;
-// nbp rounds nb up to a multiple of 8, so that the resolve's blocks keep
-// block % 8 as their XCD), the rest resolve prev against hist into resolved
-// (or copy prev there when copy is set). The resolve's blocks come last, so
-// they fill the render's tail, when fewer and fewer of its tiles are left.
+// The render of frame f and the resolve of frame f - 1 of n_views views in
+// one launch (cloud_render_resolve): blocks [0, nbp) render (nb of them are
+// tiles; nbp rounds nb up to a multiple of 8, so that the resolve's blocks
+// keep block % 8 as their XCD), the rest resolve prev against hist into
+// resolved, view by view ([n_views][H][W] images; taa_tiles a view), or copy
+// prev there when copy is set. The resolve's blocks come last, so they fill
+// the render's tail, when fewer and fewer of its tiles are left.
 template <int DT, int LAYOUT, bool DETAIL>
 __global__ __launch_bounds__(256) void render_resolve_kernel(
     DevVolume vol, DevParams prm, DevCameras cams, uint32_t frame, int W, int H, int tiles_x,
     int tiles_y, int S, int L, float4* __restrict__ out, int nb, int nbp,
     const float4* __restrict__ prev, const float4* hist, float4* resolved, int taa_tiles_x,
-    int taa_tiles, float blend, int xcd_runs, int copy) {
+    int taa_tiles, int n_views, float blend, int xcd_runs, int copy) {
   if ((int)blockIdx.x < nbp) {
     if ((int)blockIdx.x < nb)
       render_block<DT, LAYOUT, DETAIL, kImage>(blockIdx.x, nb, vol, prm, cams, frame, W, H,
@@ -128,13 +129,15 @@ __global__ __launch_bounds__(256) void render_resolve_kernel(
   }
   const int t = (int)blockIdx.x - nbp;
   if (copy) {
-    // tile t of 256 pixels, row-major over the image
+    // 256 pixels of the n_views images, in memory order
     const long long i = (long long)t * 256 + threadIdx.x;
-    if (i < (long long)W * H) resolved[i] = prev[i];
+    if (i < (long long)n_views * W * H) resolved[i] = prev[i];
     return;
   }
-  taa_block<32>(xcd_runs ? xcd_walk(t, taa_tiles, 0) : t, prev, hist, resolved, W, H,
-                taa_tiles_x, blend);
+  const int tt = xcd_runs ? xcd_walk(t, taa_tiles * n_views, 0) : t;
+  const int view = tt / taa_tiles;
+  const size_t o = (size_t)view * W * H;
+  taa_block<32>(tt - view * taa_tiles, prev + o, hist + o, resolved + o, W, H, taa_tiles_x, blend);
 }
 
 template <int DT, int LAYOUT, bool DETAIL>
@@ -376,6 +379,7 @@ struct RenderResolveLaunch {
   const DevVolume& v;
   const DevParams& p;
   const DevCameras& c;
+  int n_views;
   uint32_t frame;
   int W, H;
   float* out;
@@ -391,18 +395,19 @@ struct RenderResolveLaunch {
       return hipErrorInvalidValue;
     } else {
       const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
-      const int nb = tiles_x * tiles_y, nbp = (nb + 7) / 8 * 8;
+      const int nb = tiles_x * tiles_y * n_views, nbp = (nb + 7) / 8 * 8;
       constexpr int TW = 32, TH = 256 / TW;
       const int ttx = (W + TW - 1) / TW, tty = (H + TH - 1) / TH;
-      const int taa_blocks = copy ? (int)(((long long)W * H + 255) / 256) : ttx * tty;
+      const long long px = (long long)W * H * n_views;
+      const long long taa_blocks = copy ? (px + 255) / 256 : (long long)ttx * tty * n_views;
       const TileWalk tw = tile_walk();
-      hipLaunchKernelGGL((render_resolve_kernel<DT, LAYOUT, DETAIL>), dim3(nbp + taa_blocks),
-                         dim3(256), 0, s, v, p, c, frame, W, H, tiles_x, tiles_y, tw.S, tw.L,
-                         reinterpret_cast<float4*>(out), nb, nbp,
+      hipLaunchKernelGGL((render_resolve_kernel<DT, LAYOUT, DETAIL>),
+                         dim3((unsigned)(nbp + taa_blocks)), dim3(256), 0, s, v, p, c, frame, W, H,
+                         tiles_x, tiles_y, tw.S, tw.L, reinterpret_cast<float4*>(out), nb, nbp,
                          reinterpret_cast<const float4*>(prev),
                          reinterpret_cast<const float4*>(hist),
-                         reinterpret_cast<float4*>(resolved), ttx, ttx * tty, blend,
-                         taa_xcd_runs(W, H), copy ? 1 : 0);
+                         reinterpret_cast<float4*>(resolved), ttx, ttx * tty, n_views, blend,
+                         taa_xcd_runs(W, H * n_views), copy ? 1 : 0);
       return hipGetLastError();
     }
   }
@@ -436,10 +441,10 @@ hipError_t launch_render(const DevVolume& v, int dtype, int layout, const DevPar
 }
 
 hipError_t launch_render_resolve(const DevVolume& v, int dtype, int layout, const DevParams& p,
-                                 const DevCameras& c, uint32_t frame, int W, int H, float* out,
-                                 const float* prev, const float* hist, float* resolved,
-                                 float blend, bool copy, hipStream_t s) {
-  RenderResolveLaunch f{v, p, c, frame, W, H, out, prev, hist, resolved, blend, copy, s};
+                                 const DevCameras& c, int n_views, uint32_t frame, int W, int H,
+                                 float* out, const float* prev, const float* hist,
+                                 float* resolved, float blend, bool copy, hipStream_t s) {
+  RenderResolveLaunch f{v, p, c, n_views, frame, W, H, out, prev, hist, resolved, blend, copy, s};
   return dispatch(dtype, sampler_layout(v, layout), v.detail != nullptr, kImage, f);
 }
 

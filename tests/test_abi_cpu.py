@@ -86,11 +86,14 @@ def test_argument_errors_before_any_launch(lib):
     rc = lib.cloud_render_views(ctypes.byref(vol), ctypes.byref(cam), 0, ctypes.byref(prm), 0, 8, 8,
                                 None, None)
     assert rc == _lib.CLOUD_E_INVALID and "n_views" in _lib.last_error()
-    rc = lib.cloud_render_resolve(ctypes.byref(vol), None, ctypes.byref(prm), 1, 8, 8, None, None,
-                                  None, None, ctypes.c_float(0.1), 0, None)
-    assert rc == _lib.CLOUD_E_INVALID and "camera" in _lib.last_error()
-    rc = lib.cloud_render_resolve(ctypes.byref(vol), ctypes.byref(cam), ctypes.byref(prm), 1, 8, 0,
-                                  None, None, None, None, ctypes.c_float(0.1), 0, None)
+    rc = lib.cloud_render_resolve(ctypes.byref(vol), None, 1, ctypes.byref(prm), 1, 8, 8, None,
+                                  None, None, None, ctypes.c_float(0.1), 0, None)
+    assert rc == _lib.CLOUD_E_INVALID and "cameras" in _lib.last_error()
+    rc = lib.cloud_render_resolve(ctypes.byref(vol), ctypes.byref(cam), 0, ctypes.byref(prm), 1, 8,
+                                  8, None, None, None, None, ctypes.c_float(0.1), 0, None)
+    assert rc == _lib.CLOUD_E_INVALID and "n_views" in _lib.last_error()
+    rc = lib.cloud_render_resolve(ctypes.byref(vol), ctypes.byref(cam), 1, ctypes.byref(prm), 1, 8,
+                                  0, None, None, None, None, ctypes.c_float(0.1), 0, None)
     assert rc == _lib.CLOUD_E_INVALID and "height" in _lib.last_error()
     # a successful-looking call leaves the error text of the last failure only
     assert lib.cloud_jitter_offsets(None, 0, 0, 0, None, None) == _lib.CLOUD_OK

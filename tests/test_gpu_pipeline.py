@@ -122,7 +122,7 @@ def test_pipelined_rejects_overlaps(cf):
     cam, prm = _lib.make_camera(w.camera(0)), _lib.make_params(w.params)
 
     def call(out, prev, hist, res):
-        return lib.cloud_render_resolve(ctypes.byref(vol.struct), ctypes.byref(cam),
+        return lib.cloud_render_resolve(ctypes.byref(vol.struct), ctypes.byref(cam), 1,
                                         ctypes.byref(prm), 1, W, H, out.data_ptr(),
                                         prev.data_ptr(), hist.data_ptr(), res.data_ptr(),
                                         ctypes.c_float(0.1), 1, None)
@@ -133,3 +133,33 @@ def test_pipelined_rejects_overlaps(cf):
     assert call(a, b, c, b) == _lib.CLOUD_E_INVALID and "overlaps current" in _lib.last_error()
     assert call(a, b, c, c) == _lib.CLOUD_OK       # in-place history
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n_views,size", [(3, (160, 96)), (17, (40, 24))])   # 17: two launches
+def test_pipelined_views_bitwise(cf, n_views, size):
+    import torch
+    w = scenes.workload("C2")     # cameras 45 degrees apart around C2's slab layer
+    W, H = size
+    say(f"pipeline views: {n_views} x {W}x{H}, C2 f16 quad")
+    vol = cf.device_volume(scenes.make_scene(w, dtype="f16"), layout="quad", occupancy=True)
+    frames = [0, 1, 2, 3]
+    cams = [[w.camera(f, view=v) for v in range(n_views)] for f in frames]
+    cur = torch.empty((n_views, H, W, 4), device="cuda")
+    hist = torch.zeros((n_views, H, W, 4), device="cuda")
+    seq = []
+    for k, f in enumerate(frames):
+        cf.cloud_render_views(vol, cams[k], w.params, f, W, H, out=cur)
+        for v in range(n_views):
+            cf.cloud_taa_resolve(cur[v], hist[v], hist[v], 0.1, f)
+        seq.append((to_np(cur).copy(), to_np(hist).copy()))
+    bufs = [torch.empty((n_views, H, W, 4), device="cuda") for _ in range(2)]
+    hist2 = torch.zeros((n_views, H, W, 4), device="cuda")
+    cf.cloud_render_views(vol, cams[0], w.params, frames[0], W, H, out=bufs[0])
+    for k in range(1, len(frames)):
+        out, _ = cf.cloud_render_resolve(vol, cams[k], w.params, frames[k], W, H, bufs[(k - 1) & 1],
+                                         hist2, hist2, 0.1, frames[k - 1], out=bufs[k & 1])
+        assert np.array_equal(to_np(out), seq[k][0]), ("render", k)
+        assert np.array_equal(to_np(hist2), seq[k - 1][1]), ("resolve", k - 1)
+    for v in range(n_views):
+        cf.cloud_taa_resolve(bufs[1][v], hist2[v], hist2[v], 0.1, frames[-1])
+    assert np.array_equal(to_np(hist2), seq[-1][1])

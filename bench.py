@@ -436,11 +436,12 @@ def paper_table(cf, scenes, torch, np, dtype: str, layout: str, frames=range(10,
 # ---------------------------------------------------------------------------
 
 def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_hist,
-                  seq_ms) -> dict:
+                  seq_ms, sky=None, frame_out=None) -> dict:
     """The same frames through cloud_render_resolve: each launch renders frame
     f and resolves frame f - 1 (rendered by the launch before), so a step is
-    still one render and one resolve. The resolved history after the same
-    frame sequence is compared bit for bit with the sequential run's."""
+    still one render and one resolve (and, for a display workload, the
+    composite of the resolved frame f - 1). The resolved history after the
+    same frame sequence is compared bit for bit with the sequential run's."""
     W, H, V = w.width, w.height, w.views
     shape = (V, H, W, 4) if V > 1 else (H, W, 4)
     cur = [torch.empty(shape, device=vol.base.device) for _ in range(2)]
@@ -460,6 +461,8 @@ def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_h
         else:
             cf.cloud_render_resolve(vol, cams(f), p, f, W, H, cur[(k - 1) & 1], hist, hist,
                                     w.taa_blend, state["prev"], out=cur[k & 1])
+            if sky is not None:
+                cf.cloud_composite(hist, sky, out=frame_out)   # frame f - 1 into the display
         state["prev"], state["k"] = f, k + 1
 
     for f in warm_frames(settle) + warm:
@@ -1099,9 +1102,11 @@ def main():
                      "frames_per_group": EVENT_EVERY},
         "render_kernel_timed_frames": len(sampled),
     }
-    if not args.no_pipelined and not reproject and not w.display:
+    if not args.no_pipelined and not reproject:
         line["pipelined"] = pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed,
-                                          hist if V > 1 else hist[0], ms_per_step)
+                                          hist if V > 1 else hist[0], ms_per_step,
+                                          sky if w.display else None,
+                                          frame_out if w.display else None)
     if not args.no_replay:
         line["offset_replay"] = offset_replay(cf, torch, np, w, vol, p,
                                               range(TIMED_FIRST, TIMED_FIRST + 4))

@@ -107,6 +107,11 @@ __global__ __launch_bounds__(256) void render_kernel(DevVolume vol, DevParams pr
                                          tiles_x, tiles_y, S, L, out, counts, trace, depth);
 }
 
+// The fused kernel's resolve takes two pixels a thread (32 x 16 tiles): its
+// workgroups carry the render's register allocation, so fewer of them fit a
+// CU than of the plain resolve's, and each needs more loads in flight.
+constexpr int kFusedRows = 2;
+
 // The render of frame f and the resolve of frame f - 1 of n_views views in
 // one launch (cloud_render_resolve): blocks [0, nbp) render (nb of them are
 // tiles; nbp rounds nb up to a multiple of 8, so that the resolve's blocks
@@ -137,7 +142,8 @@ __global__ __launch_bounds__(256) void render_resolve_kernel(
   const int tt = xcd_runs ? xcd_walk(t, taa_tiles * n_views, 0) : t;
   const int view = tt / taa_tiles;
   const size_t o = (size_t)view * W * H;
-  taa_block<32>(tt - view * taa_tiles, prev + o, hist + o, resolved + o, W, H, taa_tiles_x, blend);
+  taa_block_rows<32, kFusedRows>(tt - view * taa_tiles, prev + o, hist + o, resolved + o, W, H,
+                                 taa_tiles_x, blend);
 }
 
 template <int DT, int LAYOUT, bool DETAIL>
@@ -396,7 +402,7 @@ struct RenderResolveLaunch {
     } else {
       const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
       const int nb = tiles_x * tiles_y * n_views, nbp = (nb + 7) / 8 * 8;
-      constexpr int TW = 32, TH = 256 / TW;
+      constexpr int TW = 32, TH = kFusedRows * 256 / TW;   // taa_block_rows's tiles
       const int ttx = (W + TW - 1) / TW, tty = (H + TH - 1) / TH;
       const long long px = (long long)W * H * n_views;
       const long long taa_blocks = copy ? (px + 255) / 256 : (long long)ttx * tty * n_views;

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import gc
 import json
 import math
 import multiprocessing as mp
@@ -467,8 +468,12 @@ def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_h
 
     for f in warm_frames(settle) + warm:
         step(f)
+    # the measurement legs before this one leave large host arrays behind:
+    # collect them now, not inside the timed loop
+    gc.collect()
     torch.cuda.synchronize()
     a, b = TimingEvent(), TimingEvent()
+    gc.disable()
     t0 = time.perf_counter()
     a.record()
     for f in timed:
@@ -476,6 +481,7 @@ def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_h
     b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     # the last frame's resolve, outside the timed region (the first timed
     # launch resolved the last warm-up frame instead)
     last = cur[(state["k"] - 1) & 1]
@@ -1043,13 +1049,16 @@ def main():
     settle = max(0, SETTLE_FRAMES - args.warmup)
     for f in warm_frames(settle) + warm:
         frame(f)
+    gc.collect()
     torch.cuda.synchronize()
+    gc.disable()   # no collection pause inside the timed loop
     t0 = time.perf_counter()
     for k, f in enumerate(timed):
         frame(f, ev.get(k))
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
 
     render_ms = float(np.mean([a.elapsed_time(b) for a, b in ev.values()]))
     # mean frame time of each group of EVENT_EVERY frames (the last may be shorter)

@@ -108,7 +108,7 @@ static __shared__ uint32_t s_occupancy[kOccupancyWords];
 // packed planes z; for the quad layout s_terms[3 kTabAxis + z] is the z term
 // of the next plane up, min(z + 1, nz - 1), so that both planes of a lookup
 // come from one table address.
-static __shared__ uint32_t s_terms[4 * kTabAxis];
+static __shared__ __attribute__((aligned(16))) uint32_t s_terms[4 * kTabAxis];
 
 __device__ __forceinline__ uint32_t packed_term(int i, int sh, int stride, int low_shift,
                                                 int entry_shift) {

@@ -142,8 +142,12 @@ __global__ __launch_bounds__(256) void render_resolve_kernel(
   const int tt = xcd_runs ? xcd_walk(t, taa_tiles * n_views, 0) : t;
   const int view = tt / taa_tiles;
   const size_t o = (size_t)view * W * H;
-  taa_block_rows<32, kFusedRows>(tt - view * taa_tiles, prev + o, hist + o, resolved + o, W, H,
-                                 taa_tiles_x, blend);
+  // the resolve's tile is staged in the render's table area: a workgroup
+  // runs one part or the other, so the launch holds no more LDS than a render
+  constexpr int TH = kFusedRows * 256 / 32;
+  static_assert(sizeof(float4) * (TH + 2) * 34 <= sizeof(s_terms), "resolve tile exceeds the tables");
+  taa_block_rows<32, kFusedRows>(reinterpret_cast<float4(*)[34]>(s_terms), tt - view * taa_tiles,
+                                 prev + o, hist + o, resolved + o, W, H, taa_tiles_x, blend);
 }
 
 template <int DT, int LAYOUT, bool DETAIL>

@@ -17,12 +17,13 @@ namespace cloud {
 // in flight a wavefront, for a kernel whose register allocation holds few
 // wavefronts. Every thread of the workgroup must call it (it holds a
 // barrier).
+// tile is the LDS staging area, (R * 256 / TW + 2) rows of TW + 2 pixels.
 template <int TW, int R>
-__device__ __forceinline__ void taa_block_rows(int t, const float4* __restrict__ cur,
-                                               const float4* hist, float4* out, int W, int H,
-                                               int tiles_x, float blend) {
+__device__ __forceinline__ void taa_block_rows(float4 (*tile)[TW + 2], int t,
+                                               const float4* __restrict__ cur, const float4* hist,
+                                               float4* out, int W, int H, int tiles_x,
+                                               float blend) {
   constexpr int TH = R * 256 / TW;
-  __shared__ float4 tile[TH + 2][TW + 2];
   const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
   const int bx = txi * TW, by = tyi * TH;
   for (int i = threadIdx.x; i < (TH + 2) * (TW + 2); i += 256) {
@@ -60,11 +61,13 @@ __device__ __forceinline__ void taa_block_rows(int t, const float4* __restrict__
 }
 
 
-// One pixel a thread: tiles of 256 pixels, TW wide.
+// One pixel a thread: tiles of 256 pixels, TW wide, staged in an LDS array
+// of their own.
 template <int TW>
 __device__ __forceinline__ void taa_block(int t, const float4* __restrict__ cur, const float4* hist,
                                           float4* out, int W, int H, int tiles_x, float blend) {
-  taa_block_rows<TW, 1>(t, cur, hist, out, W, H, tiles_x, blend);
+  __shared__ float4 tile[256 / TW + 2][TW + 2];
+  taa_block_rows<TW, 1>(tile, t, cur, hist, out, W, H, tiles_x, blend);
 }
 
 }  // namespace cloud

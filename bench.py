@@ -443,6 +443,9 @@ def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_h
     still one render and one resolve (and, for a display workload, the
     composite of the resolved frame f - 1). The resolved history after the
     same frame sequence is compared bit for bit with the sequential run's."""
+    # the measurement legs before this one leave large host arrays behind
+    # (lookup traces): collect them now, not in a pause inside the timed loop
+    gc.collect()
     W, H, V = w.width, w.height, w.views
     shape = (V, H, W, 4) if V > 1 else (H, W, 4)
     cur = [torch.empty(shape, device=vol.base.device) for _ in range(2)]
@@ -468,12 +471,8 @@ def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_h
 
     for f in warm_frames(settle) + warm:
         step(f)
-    # the measurement legs before this one leave large host arrays behind:
-    # collect them now, not inside the timed loop
-    gc.collect()
     torch.cuda.synchronize()
     a, b = TimingEvent(), TimingEvent()
-    gc.disable()
     t0 = time.perf_counter()
     a.record()
     for f in timed:
@@ -481,7 +480,6 @@ def pipelined_leg(cf, torch, np, w, vol, p, settle, warm, timed, lk_timed, seq_h
     b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gc.enable()
     # the last frame's resolve, outside the timed region (the first timed
     # launch resolved the last warm-up frame instead)
     last = cur[(state["k"] - 1) & 1]
@@ -1049,16 +1047,13 @@ def main():
     settle = max(0, SETTLE_FRAMES - args.warmup)
     for f in warm_frames(settle) + warm:
         frame(f)
-    gc.collect()
     torch.cuda.synchronize()
-    gc.disable()   # no collection pause inside the timed loop
     t0 = time.perf_counter()
     for k, f in enumerate(timed):
         frame(f, ev.get(k))
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gc.enable()
 
     render_ms = float(np.mean([a.elapsed_time(b) for a, b in ev.values()]))
     # mean frame time of each group of EVENT_EVERY frames (the last may be shorter)

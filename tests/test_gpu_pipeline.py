@@ -163,3 +163,16 @@ def test_pipelined_views_bitwise(cf, n_views, size):
     for v in range(n_views):
         cf.cloud_taa_resolve(bufs[1][v], hist2[v], hist2[v], 0.1, frames[-1])
     assert np.array_equal(to_np(hist2), seq[-1][1])
+
+
+@pytest.mark.parametrize("size", [(1, 1), (17, 9), (3, 50), (65536, 2)])
+def test_pipelined_edge_sizes_bitwise(cf, size):
+    # a single pixel, ragged tiles in both directions, the widest image
+    w = scenes.workload("C1", jitter=1, steps=16)
+    W, H = size
+    say(f"pipeline edge size {W}x{H}")
+    vol = cf.device_volume(scenes.make_scene(w), layout="quad", occupancy=True)
+    seq, pipe, hists = chains(cf, vol, w, W, H, [0, 1, 2])
+    for k in range(3):
+        assert np.array_equal(pipe[k], seq[k][0]), ("render", k)
+        assert np.array_equal(hists[k], seq[k][1]), ("resolve", k)
